@@ -1,0 +1,98 @@
+"""Sensitivity of the oracle's pins: plant plausible mistakes in a copy of the
+oracle's C source (a dropped term, a wrong sign, a flipped comparison, a
+transposed operand), build it on the CPU, and check that the pins of
+test_oracle.py reject every one of them."""
+import os
+import subprocess
+import tempfile
+
+import pytest
+
+import oracle
+from tests import test_oracle as T
+
+MUTANTS = [
+    ("tie rule reversed", "l_wins_tie = fl < fk;", "l_wins_tie = fl > fk;"),
+    ("floor instead of first-win position", "return floor_div(num, den) + 1;",
+     "return floor_div(num, den);"),
+    ("intersection numerator sign", "- (int64_t)k * k + (int64_t)l * l",
+     "+ (int64_t)k * k - (int64_t)l * l"),
+    ("intersection numerator drops Dv[k]", "Dv[l] - Dv[k] - (int64_t)k * k",
+     "Dv[l] - (int64_t)k * k"),
+    ("intersection denominator not doubled", "int64_t den = 2 * (int64_t)(l - k);",
+     "int64_t den = (int64_t)(l - k);"),
+    ("upward sweep keeps the lower site on ties", "c->Dv[o] > db * db", "c->Dv[o] >= db * db"),
+    ("odd step drops the +1", "c->Dv[o - W] + 2 * x + 1", "c->Dv[o - W] + 2 * x"),
+    ("pop only on strict win", "if (s <= js[n - 1])", "if (s < js[n - 1])"),
+    ("last pixel start dropped", "} else if (s <= W - 1) {", "} else if (s < W - 1) {"),
+    ("brute force keeps the last tie", "if (best < 0 || d < best) {\n            best = d;\n            bestf = (int64_t)s[q].r * W + s[q].c;",
+     "if (best < 0 || d <= best) {\n            best = d;\n            bestf = (int64_t)s[q].r * W + s[q].c;"),
+    ("brute force transposes the site index", "bestf = (int64_t)s[q].r * W + s[q].c;\n        }\n    }\n    *D",
+     "bestf = (int64_t)s[q].c * W + s[q].r;\n        }\n    }\n    *D"),
+    ("fill uses j + k", "D[j] = (int32_t)(dv[k] + (int64_t)(j - k) * (j - k));",
+     "D[j] = (int32_t)(dv[k] + (int64_t)(j - k) * (j + k));"),
+    ("fill feature uses the pixel column", "F[j] = r[k] * W + k;", "F[j] = r[k] * W + j;"),
+    ("floor division rounds towards zero", "if ((a % b != 0) && (a < 0))", "if ((a % b != 0) && (a > 0))"),
+    ("polarity inverted", "return polarity ? !object : object;", "return polarity ? object : !object;"),
+    ("contour test inverted for the upper neighbour",
+     "if (r > 0 && !is_site(mask[(int64_t)(r - 1) * pitch + c], polarity)) keep = 1;",
+     "if (r > 0 && is_site(mask[(int64_t)(r - 1) * pitch + c], polarity)) keep = 1;"),
+    ("downward sweep carries the previous row, not the site row",
+     "c->R[o] = c->R[o - W];\n", "c->R[o] = i - 1;\n"),
+    ("sqrt in single precision", "(float)sqrt((double)D[q])", "sqrtf((float)D[q])"),
+    ("basic row pass ignores the feature on ties",
+     "if (best < 0 || d < best || (d == best && f < bestf)) {",
+     "if (best < 0 || d < best) {"),
+]
+
+
+def _pins():
+    yield T.test_example_mask_matches_initialisation, ()
+    yield T.test_downward_sweep_matches_fig_eedt2, ()
+    yield T.test_vertical_pass_matches_fig_eedt_b, ()
+    for fn in ("brute", "brute_contour", "separable", "basic_rows"):
+        yield T.test_final_matches_fig_eedt_c, (fn,)
+    for fn in ("brute", "separable", "basic_rows"):
+        yield T.test_single_site_matches_fig_euclidean, (fn,)
+    yield T.test_propagation_row1_parabolas_and_kstar, ()
+    yield T.test_envelope_trace_row1, ()
+    yield T.test_all_oracle_forms_agree_on_small_masks, ()
+    yield T.test_tiny_brute_force_by_enumeration, ()
+    yield T.test_no_site_gives_sentinel, ()
+    yield T.test_all_sites_zero_and_own_index, ()
+    yield T.test_corner_site_closed_form, ()
+    yield T.test_single_site_anywhere_separable, ()
+    yield T.test_sites_in_one_row_reduce_to_1d, ()
+    yield T.test_invariants_on_generated_masks, ()
+    yield T.test_sqrt_epilogue, ()
+
+
+def _failures(lib):
+    failed = []
+    with oracle.using(lib):
+        for fn, args in _pins():
+            try:
+                fn(*args)
+            except Exception:  # an assertion or a value error both reject
+                failed.append(fn.__name__)
+    return failed
+
+
+def test_unmutated_source_passes_every_pin(tmp_path):
+    so = tmp_path / "liboracle_clean.so"
+    subprocess.check_call(["gcc", "-O1", "-std=c11", "-fPIC", "-shared", "-pthread",
+                           oracle.SRC, "-o", str(so), "-lm"])
+    assert _failures(oracle.bind(str(so))) == []
+
+
+@pytest.mark.parametrize("name,old,new", MUTANTS, ids=[m[0] for m in MUTANTS])
+def test_pins_reject_planted_mistake(name, old, new, tmp_path):
+    src = open(oracle.SRC).read()
+    assert src.count(old) == 1, f"mutation site not unique: {name}"
+    mut = tmp_path / "mutant.c"
+    mut.write_text(src.replace(old, new))
+    so = tmp_path / "libmutant.so"
+    subprocess.check_call(["gcc", "-O1", "-std=c11", "-fPIC", "-shared", "-pthread",
+                           str(mut), "-o", str(so), "-lm"])
+    failed = _failures(oracle.bind(str(so)))
+    assert failed, f"no pin rejects the planted mistake: {name}"
