@@ -1,0 +1,136 @@
+/*
+ * edt.h -- C ABI of libedt, an MI355X (gfx950) implementation of the exact
+ * Euclidean distance transform and feature transform of binary images
+ * (T. Strutz, "The Distance Transform and its Computation -- An
+ * Introduction", arXiv 2106.03503).
+ *
+ * The operation (Section 1.1 and Section 3 of the paper): given a binary image
+ * and a choice of direction, every pixel receives the squared Euclidean
+ * distance to the nearest "site" (Eq. eq_squaredEuclid), and optionally the
+ * index of that site (the feature transform; the assignment k* of Section 3.3,
+ * which partitions the image into the Voronoi regions of Figures fig_voronoi
+ * and fig_blobs).  The square root may be drawn afterwards (Section 3.1).
+ *
+ * Conventions shared by every entry point:
+ *   - Image layout: row-major; H rows (the paper's M), W columns (its L);
+ *     1 <= H, W <= EDT_MAX_SIDE.  Row i, column j are 0-based.
+ *   - Mask: uint8, byte 0 = background, any other value = object pixel
+ *     (Section 1.1: a binary image holds one of two values per pixel).
+ *     mask_pitch is the distance in BYTES between row starts (>= W).
+ *   - polarity EDT_TO_OBJECT: sites are the object pixels, i.e. every pixel
+ *     gets its distance to the nearest object pixel (Figure fig_examples(c));
+ *     EDT_TO_BACKGROUND: sites are the background pixels (Figure
+ *     fig_examples(b)).  There is no implicit site outside the image.
+ *   - Outputs: int32, row-major, out_pitch in ELEMENTS between row starts
+ *     (>= W).  dist_sq = d^2 (0 exactly at sites); feature = r*W + c, the
+ *     0-based row-major index of the nearest site, with ties between equally
+ *     near sites broken towards the SMALLEST index.  Where the image holds no
+ *     site at all, dist_sq = EDT_INF_SQ and feature = EDT_NO_SITE (the paper's
+ *     "sufficiently large" initial value, Section 3.1).
+ *   - Pointers are DEVICE pointers unless marked "host".  The caller allocates
+ *     and owns all device memory (masks, outputs, workspaces); the library
+ *     never allocates or frees it.  Handles (plans) are owned by the library
+ *     and released by the caller through the matching destroy call.
+ *   - stream is a hipStream_t passed as void* (NULL = the default stream).
+ *     Work is enqueued on it asynchronously; arguments are validated
+ *     synchronously before anything is enqueued, and an error leaves the
+ *     outputs untouched.  A launch failure returns EDT_ERR_DEVICE.
+ *   - No entry point aborts, throws or prints.
+ */
+#ifndef EDT_H
+#define EDT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define EDT_ABI_VERSION 1
+
+typedef int32_t edt_status;
+#define EDT_OK 0
+#define EDT_ERR_INVALID_ARG (-1)   /* null pointer, bad pitch, bad enum, short workspace */
+#define EDT_ERR_UNSUPPORTED (-2)   /* a metric this build does not provide */
+#define EDT_ERR_TOO_LARGE (-3)     /* H or W outside [1, EDT_MAX_SIDE] */
+#define EDT_ERR_OUT_OF_MEMORY (-4) /* a host-side allocation failed */
+#define EDT_ERR_DEVICE (-7)        /* a HIP call or kernel launch failed */
+
+#define EDT_TO_OBJECT 0
+#define EDT_TO_BACKGROUND 1
+
+#define EDT_METRIC_EUCLIDEAN_SQ 0
+
+#define EDT_INF_SQ INT32_MAX /* dist_sq where the image has no site */
+#define EDT_NO_SITE (-1)     /* feature where the image has no site */
+#define EDT_MAX_SIDE 32767   /* row indices travel as int16 between passes */
+
+/* Version of this ABI (EDT_ABI_VERSION of the build). */
+int32_t edt_abi_version(void);
+
+/* Static, human-readable name of a status code; never NULL. */
+const char *edt_status_string(edt_status s);
+
+/* Bytes of device workspace that edt_sq / edt_feature need for an H x W image
+ * (want_feature does not change the size in this build).  Returns 0 when H or
+ * W is outside [1, EDT_MAX_SIDE]. */
+size_t edt_workspace_bytes(int32_t H, int32_t W, int32_t want_feature);
+
+/* Exact squared Euclidean distance transform (Section 3: the vertical pass of
+ * Section 3.1, then per row the lower envelope of parabolas of Section 3.3.1,
+ * Eq. eq_parabola and Eq. eq_intersection).
+ *   mask        device, uint8, H x W with row pitch mask_pitch bytes
+ *   polarity    EDT_TO_OBJECT or EDT_TO_BACKGROUND
+ *   metric      EDT_METRIC_EUCLIDEAN_SQ (anything else: EDT_ERR_UNSUPPORTED)
+ *   dist_sq     device, int32, H x W with row pitch out_pitch elements; written
+ *   workspace   device, at least edt_workspace_bytes(H, W, 0) bytes, 256-byte
+ *               aligned; contents on entry are ignored and on exit undefined
+ * The workspace must not be shared by calls that may overlap in time. */
+edt_status edt_sq(const uint8_t *mask, int32_t H, int32_t W, int64_t mask_pitch,
+                  int32_t polarity, int32_t metric, int32_t *dist_sq,
+                  int64_t out_pitch, void *workspace, size_t workspace_bytes,
+                  void *stream);
+
+/* Exact squared distance plus feature transform (the nearest site's index,
+ * Section 3.3 "keep track of which column contributes the minimum", extended
+ * with the site's row from the vertical pass).  Same arguments as edt_sq, plus
+ *   dist_sq     may be NULL when only the features are wanted
+ *   feature     device, int32, H x W with row pitch out_pitch elements; written */
+edt_status edt_feature(const uint8_t *mask, int32_t H, int32_t W,
+                       int64_t mask_pitch, int32_t polarity, int32_t metric,
+                       int32_t *dist_sq, int32_t *feature, int64_t out_pitch,
+                       void *workspace, size_t workspace_bytes, void *stream);
+
+/* d = sqrt(D) drawn after all squared distances are known (Section 3.1):
+ * computed in fp64 and rounded to fp32 (the nearest fp32 to the true root for
+ * every D < 2^31); EDT_INF_SQ maps to +infinity.  dist_sq and dist are device
+ * arrays of n elements (they may not overlap). */
+edt_status edt_sqrt_f32(const int32_t *dist_sq, float *dist, int64_t n,
+                        void *stream);
+
+/* ---- kernel timing (observability) ------------------------------------ */
+
+/* Total device time of one kernel of the library between edt_profile_begin
+ * and edt_profile_end. */
+typedef struct {
+    char name[48];    /* kernel name, NUL-terminated */
+    int64_t launches; /* launches timed */
+    double total_ms;  /* summed event-to-event time on the launch streams */
+} edt_kernel_time;
+
+/* Start timing: from now on every kernel the library launches (from any
+ * thread, on any stream) is bracketed by two HIP events recorded on its own
+ * stream.  Clears earlier records. */
+edt_status edt_profile_begin(void);
+
+/* Stop timing, wait for the recorded events and write up to capacity per-kernel
+ * totals to out (host); *count (host) receives the number of distinct kernels
+ * timed.  Returns EDT_ERR_DEVICE if an event could not be read. */
+edt_status edt_profile_end(edt_kernel_time *out, int32_t capacity, int32_t *count);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* EDT_H */

@@ -1,0 +1,186 @@
+"""ctypes marshalling for libedt.so (argument checks and pointers only)."""
+from __future__ import annotations
+
+import ctypes
+import os
+
+# torch first: its HIP runtime must be the one libedt.so binds to, so that the
+# streams and device pointers torch hands over are valid in the library.
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(HERE, "libedt.so")
+
+EDT_OK = 0
+EDT_TO_OBJECT = 0
+EDT_TO_BACKGROUND = 1
+EDT_METRIC_EUCLIDEAN_SQ = 0
+EDT_INF_SQ = 2**31 - 1
+EDT_NO_SITE = -1
+
+
+class EDTError(RuntimeError):
+    def __init__(self, status: int, what: str):
+        self.status = status
+        super().__init__(f"{what}: {status_string(status)} ({status})")
+
+
+def library_path() -> str:
+    return _LIB_PATH
+
+
+def _load():
+    if not os.path.exists(_LIB_PATH):
+        raise ImportError(
+            f"{_LIB_PATH} is not built; run __graft_entry__.build() "
+            "(or python paper_2106_03503_amd/build.py)")
+    lib = ctypes.CDLL(_LIB_PATH)
+    P, i32, i64, sz = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_size_t
+    lib.edt_abi_version.argtypes = []
+    lib.edt_abi_version.restype = i32
+    lib.edt_status_string.argtypes = [i32]
+    lib.edt_status_string.restype = ctypes.c_char_p
+    lib.edt_workspace_bytes.argtypes = [i32, i32, i32]
+    lib.edt_workspace_bytes.restype = sz
+    lib.edt_sq.argtypes = [P, i32, i32, i64, i32, i32, P, i64, P, sz, P]
+    lib.edt_sq.restype = i32
+    lib.edt_feature.argtypes = [P, i32, i32, i64, i32, i32, P, P, i64, P, sz, P]
+    lib.edt_feature.restype = i32
+    lib.edt_sqrt_f32.argtypes = [P, P, i64, P]
+    lib.edt_sqrt_f32.restype = i32
+    lib.edt_profile_begin.argtypes = []
+    lib.edt_profile_begin.restype = i32
+    lib.edt_profile_end.argtypes = [P, i32, P]
+    lib.edt_profile_end.restype = i32
+    return lib
+
+
+class KernelTime(ctypes.Structure):
+    _fields_ = [("name", ctypes.c_char * 48), ("launches", ctypes.c_int64),
+                ("total_ms", ctypes.c_double)]
+
+
+_lib = _load()
+lib = _lib  # exported for tests of the raw ABI
+
+
+def abi_version() -> int:
+    return _lib.edt_abi_version()
+
+
+def status_string(status: int) -> str:
+    return _lib.edt_status_string(status).decode()
+
+
+def workspace_bytes(H: int, W: int, want_feature: bool = True) -> int:
+    return int(_lib.edt_workspace_bytes(H, W, int(want_feature)))
+
+
+def _check(status: int, what: str) -> None:
+    if status != EDT_OK:
+        raise EDTError(status, what)
+
+
+def _stream_ptr(stream) -> int:
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return int(stream.cuda_stream)
+
+
+def _check_mask(mask: torch.Tensor):
+    if not isinstance(mask, torch.Tensor) or mask.dim() != 2:
+        raise ValueError("mask must be a 2-D torch tensor")
+    if mask.dtype not in (torch.uint8, torch.bool):
+        raise ValueError("mask must be uint8 (0 = background, nonzero = object)")
+    if not mask.is_cuda:
+        raise ValueError("mask must be on a GPU device")
+    if mask.dtype == torch.bool:
+        mask = mask.view(torch.uint8)
+    if mask.stride(1) != 1:
+        mask = mask.contiguous()
+    return mask
+
+
+def _check_out(t, H, W, device, name):
+    if t is None:
+        return torch.empty((H, W), dtype=torch.int32, device=device)
+    if t.dtype != torch.int32 or t.shape != (H, W) or t.device != device or t.stride(1) != 1:
+        raise ValueError(f"{name} must be an int32 {H}x{W} tensor on {device} with unit column stride")
+    return t
+
+
+def _workspace(H, W, want_feature, device, workspace):
+    need = workspace_bytes(H, W, want_feature)
+    if need == 0:
+        raise EDTError(-3, "workspace")
+    if workspace is None:
+        return torch.empty(need, dtype=torch.uint8, device=device)
+    if workspace.numel() * workspace.element_size() < need or workspace.device != device:
+        raise ValueError(f"workspace needs {need} bytes on {device}")
+    return workspace
+
+
+def sq(mask: torch.Tensor, polarity: int = EDT_TO_OBJECT, metric: int = EDT_METRIC_EUCLIDEAN_SQ,
+       out: torch.Tensor | None = None, workspace: torch.Tensor | None = None,
+       stream=None) -> torch.Tensor:
+    """Squared Euclidean distance of every pixel to the nearest site (int32)."""
+    mask = _check_mask(mask)
+    H, W = mask.shape
+    out = _check_out(out, H, W, mask.device, "out")
+    if out.stride(0) < W:
+        raise ValueError("out row pitch must be >= W")
+    ws = _workspace(H, W, False, mask.device, workspace)
+    _check(_lib.edt_sq(mask.data_ptr(), H, W, mask.stride(0), polarity, metric,
+                       out.data_ptr(), out.stride(0), ws.data_ptr(),
+                       ws.numel() * ws.element_size(), _stream_ptr(stream)), "edt_sq")
+    return out
+
+
+def feature(mask: torch.Tensor, polarity: int = EDT_TO_OBJECT,
+            metric: int = EDT_METRIC_EUCLIDEAN_SQ, want_dist: bool = True,
+            out_dist: torch.Tensor | None = None, out_feat: torch.Tensor | None = None,
+            workspace: torch.Tensor | None = None, stream=None):
+    """(squared distance, nearest-site linear index r*W + c); the distance is
+    None when want_dist is False."""
+    mask = _check_mask(mask)
+    H, W = mask.shape
+    F = _check_out(out_feat, H, W, mask.device, "out_feat")
+    D = _check_out(out_dist, H, W, mask.device, "out_dist") if want_dist else None
+    if D is not None and D.stride(0) != F.stride(0):
+        raise ValueError("out_dist and out_feat must share one row pitch")
+    ws = _workspace(H, W, True, mask.device, workspace)
+    _check(_lib.edt_feature(mask.data_ptr(), H, W, mask.stride(0), polarity, metric,
+                            D.data_ptr() if D is not None else None, F.data_ptr(),
+                            F.stride(0), ws.data_ptr(), ws.numel() * ws.element_size(),
+                            _stream_ptr(stream)), "edt_feature")
+    return D, F
+
+
+def sqrt_f32(dist_sq: torch.Tensor, out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+    """float32 sqrt of int32 squared distances (EDT_INF_SQ -> +inf)."""
+    if dist_sq.dtype != torch.int32 or not dist_sq.is_cuda or not dist_sq.is_contiguous():
+        raise ValueError("dist_sq must be a contiguous int32 GPU tensor")
+    if out is None:
+        out = torch.empty(dist_sq.shape, dtype=torch.float32, device=dist_sq.device)
+    elif out.dtype != torch.float32 or out.shape != dist_sq.shape or not out.is_contiguous():
+        raise ValueError("out must be a contiguous float32 tensor of the same shape")
+    _check(_lib.edt_sqrt_f32(dist_sq.data_ptr(), out.data_ptr(), dist_sq.numel(),
+                             _stream_ptr(stream)), "edt_sqrt_f32")
+    return out
+
+
+def profile_begin() -> None:
+    """Start per-kernel event timing inside the library."""
+    _check(_lib.edt_profile_begin(), "edt_profile_begin")
+
+
+def profile_end() -> dict:
+    """Stop timing; {kernel name: (launches, total milliseconds)}."""
+    cap = 64
+    arr = (KernelTime * cap)()
+    n = ctypes.c_int32(0)
+    _check(_lib.edt_profile_end(ctypes.cast(arr, ctypes.c_void_p), cap,
+                                ctypes.cast(ctypes.pointer(n), ctypes.c_void_p)),
+           "edt_profile_end")
+    return {arr[q].name.decode(): (int(arr[q].launches), float(arr[q].total_ms))
+            for q in range(min(n.value, cap))}

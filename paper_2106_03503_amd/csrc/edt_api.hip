@@ -1,0 +1,112 @@
+// C ABI of libedt (declared in include/edt.h): argument validation, workspace
+// layout and the launch sequence of one transform.
+#include "../../include/edt.h"
+#include "edt_internal.h"
+
+#include <math.h>
+
+namespace edt {
+namespace {
+
+__global__ __launch_bounds__(256) void k_sqrt(const int32_t* __restrict__ D,
+                                              float* __restrict__ out, int64_t n) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < n; q += stride) {
+        const int32_t d = D[q];
+        out[q] = d == INT32_MAX ? INFINITY : (float)sqrt((double)d);
+    }
+}
+
+}  // namespace
+
+hipError_t launch_sqrt(const int32_t* D, float* out, int64_t n, hipStream_t stream) {
+    if (n == 0) return hipSuccess;
+    int64_t blocks = (n + 255) / 256;
+    if (blocks > 8192) blocks = 8192;
+    EDT_LAUNCH(k_sqrt, dim3((unsigned)blocks), dim3(256), 0, stream, D, out, n);
+    return hipGetLastError();
+}
+
+static edt_status check_image(const uint8_t* mask, int32_t H, int32_t W,
+                              int64_t mask_pitch, int32_t polarity, int32_t metric,
+                              int64_t out_pitch) {
+    if (H < 1 || W < 1 || H > EDT_MAX_SIDE || W > EDT_MAX_SIDE) return EDT_ERR_TOO_LARGE;
+    if (!mask || mask_pitch < W || out_pitch < W) return EDT_ERR_INVALID_ARG;
+    if (polarity != EDT_TO_OBJECT && polarity != EDT_TO_BACKGROUND) return EDT_ERR_INVALID_ARG;
+    if (metric != EDT_METRIC_EUCLIDEAN_SQ) {
+        if (metric < 0 || metric > 3) return EDT_ERR_INVALID_ARG;
+        return EDT_ERR_UNSUPPORTED;
+    }
+    return EDT_OK;
+}
+
+static edt_status run(const uint8_t* mask, int32_t H, int32_t W, int64_t mask_pitch,
+                      int32_t polarity, int32_t metric, int32_t* dist, int32_t* feat,
+                      int64_t out_pitch, void* workspace, size_t workspace_bytes,
+                      void* stream) {
+    edt_status st = check_image(mask, H, W, mask_pitch, polarity, metric, out_pitch);
+    if (st != EDT_OK) return st;
+    if (!dist && !feat) return EDT_ERR_INVALID_ARG;
+    const Layout L = layout_for(H, W);
+    if (!workspace || workspace_bytes < L.total) return EDT_ERR_INVALID_ARG;
+    if ((reinterpret_cast<uintptr_t>(workspace) & 255) != 0) return EDT_ERR_INVALID_ARG;
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    uint8_t* ws = static_cast<uint8_t*>(workspace);
+    if (launch_column_pass(mask, H, W, mask_pitch, polarity, ws, L, s) != hipSuccess)
+        return EDT_ERR_DEVICE;
+    if (launch_row_pass(reinterpret_cast<const int16_t*>(ws + L.rstar), H, W, dist, feat,
+                        out_pitch, ws, L, s) != hipSuccess)
+        return EDT_ERR_DEVICE;
+    return EDT_OK;
+}
+
+}  // namespace edt
+
+extern "C" {
+
+int32_t edt_abi_version(void) { return EDT_ABI_VERSION; }
+
+const char* edt_status_string(edt_status s) {
+    switch (s) {
+        case EDT_OK: return "ok";
+        case EDT_ERR_INVALID_ARG: return "invalid argument";
+        case EDT_ERR_UNSUPPORTED: return "unsupported metric";
+        case EDT_ERR_TOO_LARGE: return "image too large";
+        case EDT_ERR_OUT_OF_MEMORY: return "out of host memory";
+        case EDT_ERR_DEVICE: return "device error";
+        default: return "unknown status";
+    }
+}
+
+size_t edt_workspace_bytes(int32_t H, int32_t W, int32_t want_feature) {
+    (void)want_feature;
+    if (H < 1 || W < 1 || H > EDT_MAX_SIDE || W > EDT_MAX_SIDE) return 0;
+    return edt::layout_for(H, W).total;
+}
+
+edt_status edt_sq(const uint8_t* mask, int32_t H, int32_t W, int64_t mask_pitch,
+                  int32_t polarity, int32_t metric, int32_t* dist_sq, int64_t out_pitch,
+                  void* workspace, size_t workspace_bytes, void* stream) {
+    if (!dist_sq) return EDT_ERR_INVALID_ARG;
+    return edt::run(mask, H, W, mask_pitch, polarity, metric, dist_sq, nullptr, out_pitch,
+                    workspace, workspace_bytes, stream);
+}
+
+edt_status edt_feature(const uint8_t* mask, int32_t H, int32_t W, int64_t mask_pitch,
+                       int32_t polarity, int32_t metric, int32_t* dist_sq,
+                       int32_t* feature, int64_t out_pitch, void* workspace,
+                       size_t workspace_bytes, void* stream) {
+    if (!feature) return EDT_ERR_INVALID_ARG;
+    return edt::run(mask, H, W, mask_pitch, polarity, metric, dist_sq, feature, out_pitch,
+                    workspace, workspace_bytes, stream);
+}
+
+edt_status edt_sqrt_f32(const int32_t* dist_sq, float* dist, int64_t n, void* stream) {
+    if (n < 0 || (n > 0 && (!dist_sq || !dist))) return EDT_ERR_INVALID_ARG;
+    if (edt::launch_sqrt(dist_sq, dist, n, reinterpret_cast<hipStream_t>(stream)) !=
+        hipSuccess)
+        return EDT_ERR_DEVICE;
+    return EDT_OK;
+}
+
+}  // extern "C"

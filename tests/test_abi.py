@@ -1,0 +1,92 @@
+"""The C ABI on the CPU: the library loads, exports every entry point that
+include/edt.h declares, and rejects bad arguments before touching a device."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "edt.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(edt_[a-z0-9_]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def edt():
+    import paper_2106_03503_amd as edt
+    return edt
+
+
+def test_header_declares_entry_points():
+    names = declared_functions()
+    for must in ("edt_sq", "edt_feature", "edt_sqrt_f32", "edt_workspace_bytes",
+                 "edt_status_string", "edt_abi_version"):
+        assert must in names
+
+
+def test_library_exports_every_declared_symbol(edt):
+    lib = ctypes.CDLL(edt.library_path())
+    missing = [n for n in declared_functions() if not hasattr(lib, n)]
+    assert missing == []
+
+
+def test_abi_version_and_status_strings(edt):
+    from paper_2106_03503_amd import _lib
+    assert edt.abi_version() == 1
+    for code, text in ((0, "ok"), (-1, "invalid argument"), (-2, "unsupported metric"),
+                       (-3, "image too large"), (-7, "device error")):
+        assert _lib.status_string(code) == text
+    assert _lib.status_string(12345) == "unknown status"
+
+
+def test_workspace_bytes(edt):
+    assert edt.workspace_bytes(0, 10) == 0
+    assert edt.workspace_bytes(10, 0) == 0
+    assert edt.workspace_bytes(32768, 10) == 0
+    assert edt.workspace_bytes(10, 32768) == 0
+    a = edt.workspace_bytes(100, 100)
+    b = edt.workspace_bytes(200, 100)
+    assert 0 < a < b
+    # at least the int16 intermediate of 2 bytes per pixel
+    assert edt.workspace_bytes(16384, 16384) >= 2 * 16384 * 16384
+
+
+def test_argument_validation_returns_before_any_launch(edt):
+    from paper_2106_03503_amd import _lib
+    lib = _lib.lib
+    fake = 0x1000  # never dereferenced: every call below fails validation
+    ws = edt.workspace_bytes(10, 10)
+    # sizes
+    assert lib.edt_sq(fake, 0, 10, 10, 0, 0, fake, 10, fake, ws, None) == -3
+    assert lib.edt_sq(fake, 10, 40000, 40000, 0, 0, fake, 40000, fake, ws, None) == -3
+    # null pointers and pitches
+    assert lib.edt_sq(None, 10, 10, 10, 0, 0, fake, 10, fake, ws, None) == -1
+    assert lib.edt_sq(fake, 10, 10, 10, 0, 0, None, 10, fake, ws, None) == -1
+    assert lib.edt_sq(fake, 10, 10, 9, 0, 0, fake, 10, fake, ws, None) == -1
+    assert lib.edt_sq(fake, 10, 10, 10, 0, 0, fake, 9, fake, ws, None) == -1
+    assert lib.edt_feature(fake, 10, 10, 10, 0, 0, fake, None, 10, fake, ws, None) == -1
+    # enums
+    assert lib.edt_sq(fake, 10, 10, 10, 2, 0, fake, 10, fake, ws, None) == -1
+    assert lib.edt_sq(fake, 10, 10, 10, 0, 1, fake, 10, fake, ws, None) == -2
+    assert lib.edt_sq(fake, 10, 10, 10, 0, 9, fake, 10, fake, ws, None) == -1
+    # workspace: short, missing, misaligned
+    assert lib.edt_sq(fake, 10, 10, 10, 0, 0, fake, 10, fake, ws - 1, None) == -1
+    assert lib.edt_sq(fake, 10, 10, 10, 0, 0, fake, 10, None, ws, None) == -1
+    assert lib.edt_sq(fake, 10, 10, 10, 0, 0, fake, 10, fake + 8, ws, None) == -1
+    # sqrt
+    assert lib.edt_sqrt_f32(fake, fake, -1, None) == -1
+    assert lib.edt_sqrt_f32(None, fake, 5, None) == -1
+    assert lib.edt_sqrt_f32(None, None, 0, None) == 0  # empty: nothing to do
+
+
+def test_python_binding_rejects_cpu_tensors(edt):
+    import torch
+    with pytest.raises(ValueError):
+        edt.sq(torch.zeros((4, 4), dtype=torch.uint8))
+    with pytest.raises(ValueError):
+        edt.feature(torch.zeros((4, 4, 4), dtype=torch.uint8))

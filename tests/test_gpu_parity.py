@@ -1,0 +1,151 @@
+"""Bit-exact parity of the HIP path (through the C ABI) with the CPU oracle.
+
+Small and mid-size images are compared element by element with the oracle's
+separable transform (itself pinned to brute force and to the paper's tables in
+test_oracle.py) and, where cheap, with brute force directly.  Full-size
+images are compared with the oracle in full where it finishes in seconds, and
+always at sampled pixels by brute force plus invariants that hold at any size.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+
+pytestmark = pytest.mark.gpu
+
+INF_SQ = 2**31 - 1
+
+
+@pytest.fixture(scope="module")
+def edt():
+    import torch
+    import paper_2106_03503_amd as edt
+    assert torch.cuda.is_available()
+    return edt
+
+
+def run(edt, m, pol, pitch_pad=0, out_pad=0):
+    import torch
+    dev = torch.device("cuda:0")
+    H, W = m.shape
+    big = torch.zeros((H, W + pitch_pad), dtype=torch.uint8, device=dev)
+    big[:, :W] = torch.from_numpy(m).to(dev)
+    mask = big[:, :W]
+    Dbuf = torch.full((H, W + out_pad), -7, dtype=torch.int32, device=dev)
+    Fbuf = torch.full((H, W + out_pad), -7, dtype=torch.int32, device=dev)
+    D, F = edt.feature(mask, polarity=pol, out_dist=Dbuf[:, :W], out_feat=Fbuf[:, :W])
+    Dsq = edt.sq(mask, polarity=pol)
+    torch.cuda.synchronize()
+    if out_pad:
+        # the padding columns are never written
+        assert bool((Dbuf[:, W:] == -7).all()) and bool((Fbuf[:, W:] == -7).all())
+    return D.cpu().numpy(), F.cpu().numpy(), Dsq.cpu().numpy()
+
+
+def check_exact(edt, m, pol, **kw):
+    D, F, Dsq = run(edt, m, pol, **kw)
+    Do, Fo = oracle.separable(m, pol)
+    assert np.array_equal(D, Do), f"D differs on {m.shape} pol={pol}"
+    assert np.array_equal(F, Fo), f"F differs on {m.shape} pol={pol}"
+    assert np.array_equal(Dsq, Do), f"edt_sq differs on {m.shape} pol={pol}"
+    return D, F
+
+
+def test_paper_example_matches_printed_table(edt):
+    from tests.golden_io import table
+    m = workloads.paper_example()
+    D, F = check_exact(edt, m, 0)
+    assert np.array_equal(D, table("fig_eedt_c_final.txt"))
+
+
+@pytest.mark.parametrize("pol", [0, 1])
+def test_bernoulli_256_and_crop_against_brute_force(edt, pol):
+    m = workloads.bernoulli(256, 256, 0.01)
+    D, F = check_exact(edt, m, pol)
+    Db, Fb = oracle.brute(m, pol, contour_only=True)
+    assert np.array_equal(D, Db) and np.array_equal(F, Fb)
+    crop = np.ascontiguousarray(m[:64, :64])
+    Dc, Fc, _ = run(edt, crop, pol)
+    Db, Fb = oracle.brute(crop, pol)
+    assert np.array_equal(Dc, Db) and np.array_equal(Fc, Fb)
+
+
+@pytest.mark.parametrize("shape", [(1, 1), (1, 300), (300, 1), (63, 65), (64, 64), (65, 63),
+                                   (127, 129), (129, 257), (200, 513), (3, 1000)])
+@pytest.mark.parametrize("pol", [0, 1])
+def test_edge_shapes_random(edt, shape, pol):
+    rng = np.random.default_rng(hash(shape) % 1000 + pol)
+    m = (rng.random(shape) < 0.05).astype(np.uint8)
+    check_exact(edt, m, pol)
+
+
+@pytest.mark.parametrize("kind", ["empty", "full", "corner", "one_far", "one_row", "one_col"])
+@pytest.mark.parametrize("pol", [0, 1])
+def test_degenerate_masks(edt, kind, pol):
+    H, W = 150, 170
+    m = np.zeros((H, W), np.uint8)
+    if kind == "full":
+        m[:] = 1
+    elif kind == "corner":
+        m[0, 0] = 1
+    elif kind == "one_far":
+        m[H - 1, W - 1] = 1
+    elif kind == "one_row":
+        m[77, ::13] = 1
+    elif kind == "one_col":
+        m[::11, 91] = 1
+    D, F = check_exact(edt, m, pol)
+    site = (m != 0) != (pol == 1)
+    if not site.any():
+        assert np.all(D == INF_SQ) and np.all(F == -1)
+    if site.all():
+        assert np.all(D == 0)
+
+
+def test_tie_heavy_symmetric_masks(edt):
+    rng = np.random.default_rng(99)
+    for t in range(20):
+        H, W = int(rng.integers(20, 90)), int(rng.integers(20, 90))
+        q = (rng.random(((H + 1) // 2, (W + 1) // 2)) < rng.uniform(0.01, 0.2)).astype(np.uint8)
+        m = np.zeros((H, W), np.uint8)
+        m[:q.shape[0], :q.shape[1]] = q
+        m[:, W - q.shape[1]:] |= m[:, :q.shape[1]][:, ::-1]
+        m[H - q.shape[0]:, :] |= m[:q.shape[0], :][::-1, :]
+        check_exact(edt, m, t % 2)
+        Db, Fb = oracle.brute(m, t % 2)
+        D, F, _ = run(edt, m, t % 2)
+        assert np.array_equal(D, Db) and np.array_equal(F, Fb)
+
+
+def test_pitched_mask_and_outputs(edt):
+    m = workloads.bernoulli(77, 301, 0.02, seed=5)
+    check_exact(edt, m, 0, pitch_pad=37, out_pad=11)
+    check_exact(edt, m, 1, pitch_pad=1, out_pad=3)
+
+
+def test_wide_rows_use_the_global_row_slots(edt):
+    # rows wider than what the row pass keeps in LDS
+    for W, p in ((11000, 0.001), (16384, 0.0005), (20001, 0.3)):
+        m = workloads.bernoulli(70, W, p, seed=W)
+        check_exact(edt, m, 0)
+    m = workloads.points(40, 16384, n=5, seed=1)
+    check_exact(edt, m, 1)  # every column holds sites: dense wide rows
+
+
+def test_disks_mid_size_both_polarities(edt):
+    m = workloads.disks(1024, 1024, n_disks=40, rmin=3, rmax=60, p_points=1e-4, seed=3)
+    for pol in (0, 1):
+        check_exact(edt, m, pol)
+
+
+def test_sqrt_epilogue_matches_oracle(edt):
+    import torch
+    m = workloads.bernoulli(300, 400, 0.001, seed=2)
+    D, _, _ = run(edt, m, 0)
+    d = edt.sqrt_f32(torch.from_numpy(D).cuda())
+    big = torch.tensor([0, 1, 2, 3, 2**31 - 2, INF_SQ, 536805378], dtype=torch.int32).cuda()
+    d2 = edt.sqrt_f32(big)
+    torch.cuda.synchronize()
+    assert np.array_equal(d.cpu().numpy(), oracle.sqrt_f32(D))
+    assert np.array_equal(d2.cpu().numpy(), oracle.sqrt_f32(big.cpu().numpy()))
