@@ -25,15 +25,32 @@ sys.path.insert(0, ROOT)
 METRIC = "Gpixel/s exact sq-EDT+feature transform and % HBM roofline; batched vs per-image"
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published peak
 
-# Algorithmic HBM bytes per pixel of each kernel (what the kernel must move at
-# minimum given its inputs and outputs, "Roofline").
-ALGO_BYTES_PER_PX = {
-    "k_band_bits": 1.0 + 8.0 / 64,          # mask byte in, 1 site bit out
-    "k_band_carry": 8.0 / 64 + 4.0 / 64,    # site bits in, two int16 carries per band out
-    "k_nearest_row": 8.0 / 64 + 4.0 / 64 + 2.0,  # bits + carries in, int16 row out
-    "k_row_envelope": 2.0 + 8.0,            # int16 row in, int32 D + int32 F out
-}
 PATH_BYTES_PER_PX = 13.0  # 1 mask + 2 + 2 intermediate + 4 D + 4 F
+
+
+def algo_bytes(kernel: str, H: int, W: int, n: int, with_dist: bool = True) -> int:
+    """Algorithmic HBM bytes of one launch of `kernel` on an H x W image whose
+    sites occupy n columns: what the kernel must read and write at minimum
+    given its inputs and outputs ('Roofline')."""
+    nb = (H + 63) // 64
+    if kernel == "k_band_bits":          # mask in, one site bit per pixel out
+        return H * W + nb * W * 8
+    if kernel == "k_band_carry":         # site bits in, two int16 carries per band out
+        return nb * W * 8 + nb * W * 4 + W * 4
+    if kernel == "k_col_compact":        # column flags in, column list out
+        return W * 4 + n * 2
+    if kernel == "k_nearest_row":        # bits + carries of listed columns in, int16 rows out
+        return nb * n * 12 + H * n * 2
+    if kernel.startswith("k_row_"):      # int16 rows in, int32 D and F out
+        return H * n * 2 + H * W * (8 if with_dist else 4)
+    raise KeyError(kernel)
+
+
+def site_columns(mask, polarity) -> int:
+    """Number of columns holding at least one site (input statistics)."""
+    import numpy as np
+    site = (mask != 0) if polarity == 0 else (mask == 0)
+    return int(np.count_nonzero(site.any(axis=0)))
 
 WORKLOADS = {
     "points16k": dict(
@@ -168,7 +185,7 @@ def main():
     dom = max(kt, key=lambda k: kt[k][1])
     launches, total_ms = kt[dom]
     avg_ms = total_ms / launches
-    algo = ALGO_BYTES_PER_PX[dom] * px
+    algo = algo_bytes(dom, H, W, site_columns(mask_np, pol))
     achieved = algo / (avg_ms * 1e-3) / 1e9
     traffic = traffic_from_profiles(dom, args.workload)
     roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1),

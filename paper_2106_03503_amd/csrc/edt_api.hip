@@ -54,8 +54,7 @@ static edt_status run(const uint8_t* mask, int32_t H, int32_t W, int64_t mask_pi
     uint8_t* ws = static_cast<uint8_t*>(workspace);
     if (launch_column_pass(mask, H, W, mask_pitch, polarity, ws, L, s) != hipSuccess)
         return EDT_ERR_DEVICE;
-    if (launch_row_pass(reinterpret_cast<const int16_t*>(ws + L.rstar), H, W, dist, feat,
-                        out_pitch, ws, L, s) != hipSuccess)
+    if (launch_row_pass(H, W, dist, feat, out_pitch, ws, L, s) != hipSuccess)
         return EDT_ERR_DEVICE;
     return EDT_OK;
 }

@@ -1,156 +1,417 @@
-// Horizontal pass of the exact EDT (Section 3.3.1 of Strutz, arXiv
-// 2106.03503): per row, the lower envelope of the parabolas
-// D_k(j) = Dv(k) + (j - k)^2 (Eq. eq_parabola) over the columns k that hold a
-// site, then a fill of every pixel from the parabola that owns it.
+// Horizontal pass of the exact EDT (Section 3.3 of Strutz, arXiv 2106.03503):
+// per row, the lower envelope of the parabolas D_k(j) = Dv(k) + (j - k)^2
+// (Eq. eq_parabola) over the columns k that hold a site (the same list for
+// every row), then every pixel is filled from the parabola that owns it.
 //
-// Ties: the comparison between two parabolas at a pixel is lexicographic on
-// (D, feature index), feature = r*W + k, so the owner of a pixel is the nearest
-// site with the smallest row-major index.  For k < l, parabola l beats k at
-// every j >= s where s is the first integer past the crossing of Eq.
-// eq_intersection (or at it, when l wins the tie), computed with exact integer
-// floor division and clamped to [0, W].
+// Order and ties: parabolas are compared at a pixel lexicographically on
+// (D, feature index), feature = r*W + k, so every pixel is owned by its nearest
+// site with the smallest row-major index.  For columns k < l, parabola l beats
+// k on a suffix j >= s of the row; s is the first integer past the crossing of
+// Eq. eq_intersection, or the crossing itself when l has the smaller index.
+//
+// The paper builds the envelope with one left-to-right scan and a stack.  Here
+// the candidate list of a row is cut into chunks of S candidates, one per lane:
+//   1. every lane builds the envelope of its chunk with that scan, the stack
+//      kept in place over the chunk's slots;
+//   2. neighbouring envelopes are merged pairwise up a binary tree.  Two
+//      envelopes whose columns do not interleave cross only once (every
+//      parabola of the right one gains on every parabola of the left one as j
+//      grows), so the merge keeps a prefix of the left envelope and a suffix of
+//      the right one; it walks inwards from the seam, dropping a parabola of
+//      the left side when the right side's first parabola already wins where it
+//      starts, and one of the right side when the left side's last parabola
+//      still wins where it ends.  Each step removes one parabola, so the tree
+//      costs O(candidates) in total;
+//   3. the survivors are compacted in order and the row is filled, four
+//      adjacent pixels per lane and store, so that a wavefront writes 1 KiB of
+//      contiguous output per instruction.
+// All position tests compare parabola values directly; an exact integer
+// division is needed only when a parabola is stored with a new start.
 #include "edt_internal.h"
 
 namespace edt {
 namespace {
 
-// First pixel j in [0, W] at which parabola l (site row rl) beats parabola k
-// (site row rk), k < l, in row i.  W means "never inside the row".
-__device__ __forceinline__ int first_win(int k, int rk, int l, int rl, int i, int W) {
-    const int64_t dk = (int64_t)(i - rk) * (i - rk);
-    const int64_t dl = (int64_t)(i - rl) * (i - rl);
-    const int64_t num = dl - dk + (int64_t)(l - k) * (l + k);
-    const int64_t den = 2 * (int64_t)(l - k);
-    // l beats k at j iff j*den > num, or j*den == num and l has the smaller
-    // index, i.e. a smaller site row (in the same row l's column is larger, so
-    // its index is larger).  Hence s = floor((num - [l wins ties]) / den) + 1.
-    const int64_t n2 = num - (rl < rk ? 1 : 0);
-    if (n2 < 0) return 0;
-    const int64_t q = n2 / den;
-    return q + 1 < (int64_t)W ? (int)(q + 1) : W;
+// A candidate is packed as (column << 16) | site row.
+__device__ __forceinline__ int ccol(uint32_t c) { return (int)(c >> 16); }
+__device__ __forceinline__ int crow(uint32_t c) { return (int)(c & 0xFFFFu); }
+
+// Squared distance from pixel (i, j) to the site of candidate C (< 2^31 for
+// sides up to 32767).
+__device__ __forceinline__ int parab(uint32_t C, int i, int j) {
+    const int dr = i - crow(C), dc = j - ccol(C);
+    return dr * dr + dc * dc;
 }
 
-__global__ __launch_bounds__(kRowThreads) void k_row_envelope(
-    const int16_t* __restrict__ rstar, int H, int W, int32_t* __restrict__ dist,
-    int32_t* __restrict__ feat, int64_t out_pitch, uint8_t* __restrict__ scratch) {
-    extern __shared__ uint32_t lds[];
-    __shared__ int s_wave_count[kRowThreads / 64];
-    __shared__ int s_m;
-    uint32_t* cand;  // (column << 16) | site row, increasing column
-    int16_t* start;  // first pixel owned by each stacked parabola
-    if (scratch) {
-        cand = reinterpret_cast<uint32_t*>(scratch + (size_t)blockIdx.x * row_slot_bytes(W));
-    } else {
-        cand = lds;
+// Does B (a column right of A's) beat A at pixel j of row i?
+__device__ __forceinline__ bool beats(uint32_t B, uint32_t A, int i, int j) {
+    const int fb = parab(B, i, j), fa = parab(A, i, j);
+    return fb < fa || (fb == fa && crow(B) < crow(A));
+}
+
+// First pixel j in [0, W] from which B beats A (W: never inside the row).
+// B beats A at j iff j*den > num, or j*den == num and B has the smaller index
+// (a smaller site row: B's column is larger), with num and den from Eq.
+// eq_intersection; so j >= floor((num - [B wins ties]) / den) + 1.
+__device__ __forceinline__ int first_win(uint32_t A, uint32_t B, int i, int W) {
+    const int k = ccol(A), l = ccol(B), rk = crow(A), rl = crow(B);
+    const int dk = (i - rk) * (i - rk), dl = (i - rl) * (i - rl);
+    const int num = dl - dk + (l - k) * (l + k);
+    const int n2 = num - (rl < rk ? 1 : 0);
+    if (n2 < 0) return 0;
+    const unsigned q = (unsigned)n2 / (2u * (unsigned)(l - k));
+    return q + 1u < (unsigned)W ? (int)q + 1 : W;
+}
+
+// Chunk slots: logical slot l = t*S + u (slot u of lane t's chunk) is stored
+// at u*T + t, so that lanes working on their own chunks touch consecutive LDS
+// banks.
+template <int T, int S>
+struct Slots {
+    uint32_t* cand;
+    int16_t* st;
+    __device__ __forceinline__ int at(int l) const { return (l % S) * T + l / S; }
+    __device__ __forceinline__ uint32_t& c(int l) const { return cand[at(l)]; }
+    __device__ __forceinline__ int16_t& s(int l) const { return st[at(l)]; }
+};
+
+// Merge the envelope of chunk group R (first chunk g_r) into the group to its
+// left, L (first chunk g_l).  Per chunk c: survivors occupy logical slots
+// [lo, hi), nxt/prv link the non-empty chunks of a group, gf/gl hold the first
+// and last non-empty chunk of the group starting at c.  The first survivor of
+// a group always starts at pixel 0.
+template <int T, int S>
+__device__ void merge_groups(int g_l, int g_r, const Slots<T, S>& sl,
+                             int16_t* __restrict__ lo, int16_t* __restrict__ hi,
+                             int16_t* __restrict__ nxt, int16_t* __restrict__ prv,
+                             int16_t* __restrict__ gf, int16_t* __restrict__ gl, int i,
+                             int W) {
+    const int Ll = gl[g_l], Rf = gf[g_r], Rl = gl[g_r];
+    if (Rf < 0) return;
+    if (Ll < 0) {
+        gf[g_l] = (int16_t)Rf;
+        gl[g_l] = (int16_t)Rl;
+        return;
     }
-    start = reinterpret_cast<int16_t*>(cand + W);
-    const int lane = threadIdx.x & 63;
-    const int wave = threadIdx.x >> 6;
+    int ca = Ll, ia = hi[ca] - 1;
+    int cb = Rf, ib = lo[cb];
+    bool left_alive = true, right_alive = true;
+    for (;;) {
+        const uint32_t A = sl.c(ia), B = sl.c(ib);
+        if (beats(B, A, i, sl.s(ia))) {  // A is hidden wherever it owned pixels
+            if (ia > lo[ca]) {
+                --ia;
+                continue;
+            }
+            hi[ca] = lo[ca];
+            ca = prv[ca];
+            if (ca < 0) {
+                left_alive = false;
+                break;
+            }
+            ia = hi[ca] - 1;
+            continue;
+        }
+        int bend;  // first pixel after B's range in the right envelope
+        if (ib + 1 < hi[cb]) {
+            bend = sl.s(ib + 1);
+        } else {
+            const int cn = nxt[cb];
+            bend = cn >= 0 ? sl.s(lo[cn]) : W;
+        }
+        if (!beats(B, A, i, bend - 1)) {  // B is hidden wherever it owned pixels
+            if (ib + 1 < hi[cb]) {
+                ++ib;
+                continue;
+            }
+            lo[cb] = hi[cb];
+            cb = nxt[cb];
+            if (cb < 0) {
+                right_alive = false;
+                break;
+            }
+            ib = lo[cb];
+            continue;
+        }
+        sl.s(ib) = (int16_t)first_win(A, B, i, W);  // the seam
+        break;
+    }
+    if (left_alive && right_alive) {
+        hi[ca] = (int16_t)(ia + 1);
+        lo[cb] = (int16_t)ib;
+        nxt[ca] = (int16_t)cb;
+        prv[cb] = (int16_t)ca;
+        gl[g_l] = (int16_t)Rl;
+    } else if (!left_alive) {  // the right envelope alone remains
+        lo[cb] = (int16_t)ib;
+        prv[cb] = -1;
+        sl.s(ib) = 0;
+        gf[g_l] = (int16_t)cb;
+        gl[g_l] = (int16_t)Rl;
+    } else {  // the left envelope alone remains
+        hi[ca] = (int16_t)(ia + 1);
+        nxt[ca] = -1;
+        gl[g_l] = (int16_t)ca;
+    }
+}
+
+// Last index e in [lo, hi) with st[e] <= j, given st[lo] <= j.
+__device__ __forceinline__ int last_le(const int16_t* __restrict__ st, int lo, int hi, int j) {
+    int a = lo, b = hi - 1;
+    while (a < b) {
+        const int mid = (a + b + 1) >> 1;
+        if (st[mid] <= j)
+            a = mid;
+        else
+            b = mid - 1;
+    }
+    return a;
+}
+
+__device__ __forceinline__ void store4(int32_t* __restrict__ p, int j, int W, bool vec,
+                                       int v0, int v1, int v2, int v3) {
+    if (vec && j + 4 <= W) {
+        *reinterpret_cast<int4*>(p + j) = make_int4(v0, v1, v2, v3);
+    } else {
+        p[j] = v0;
+        if (j + 1 < W) p[j + 1] = v1;
+        if (j + 2 < W) p[j + 2] = v2;
+        if (j + 3 < W) p[j + 3] = v3;
+    }
+}
+
+// Row pass.  T lanes per row, S candidate slots per lane.  The sparse form
+// (one wavefront, kSparse) takes images with at most T*S candidate columns,
+// the dense form the others.  With kGlobal the candidate list lives in a
+// global-memory slot per workgroup instead of LDS.
+template <int T, int S, bool kSparse, bool kGlobal>
+__global__ __launch_bounds__(T) void k_row_envelope(
+    const int16_t* __restrict__ rc, const int16_t* __restrict__ cols,
+    const int32_t* __restrict__ meta, int H, int W, int32_t* __restrict__ dist,
+    int32_t* __restrict__ feat, int64_t out_pitch, int vec_out, uint8_t* __restrict__ slots) {
+    constexpr int NW = T / 64;
+    constexpr int CAP = kGlobal ? 1 : T * S;
+    static_assert(!kGlobal || T * S <= kWideCap, "global row slot too small");
+    static_assert((S & (S - 1)) == 0 && (T & (T - 1)) == 0, "T and S must be powers of two");
+    __shared__ uint32_t s_cand[CAP];
+    __shared__ int16_t s_st[CAP];
+    __shared__ int16_t s_lo[T], s_hi[T], s_nxt[T], s_prv[T], s_gf[T], s_gl[T];
+    __shared__ int s_wsum[NW];
+
+    const int n = meta[0];
+    if (kSparse ? (n > T * S) : (n <= kSparseMaxN)) return;  // the other form's image
+    const int pitch = meta[1];
+    uint32_t* cand;
+    int16_t* st;
+    if (kGlobal) {
+        uint8_t* slot = slots + (size_t)blockIdx.x * wide_slot_bytes(W);
+        cand = reinterpret_cast<uint32_t*>(slot);
+        st = reinterpret_cast<int16_t*>(slot + (size_t)kWideCap * 4);
+    } else {
+        cand = s_cand;
+        st = s_st;
+    }
+    const Slots<T, S> sl{cand, st};
+    const int t = threadIdx.x;
+    const int lane = t & 63, wave = t >> 6;
+    const int nchunks = (n + S - 1) / S;
+    const int base = t * S;
+    const int cnt = min(max(n - base, 0), S);
+    const bool vec = vec_out != 0;
+
+    // The candidate columns of this lane's chunk are the same in every row.
+    uint32_t colhi[S];
+#pragma unroll
+    for (int u = 0; u < S; ++u) colhi[u] = u < cnt ? ((uint32_t)(uint16_t)cols[base + u] << 16) : 0u;
 
     for (int i = blockIdx.x; i < H; i += gridDim.x) {
-        const int16_t* row = rstar + (int64_t)i * W;
-        // 1. Candidate columns (those with a site, Section 3.2.2), compacted in
-        //    column order with a wavefront ballot and a workgroup prefix.
-        int n = 0;
-        for (int c0 = 0; c0 < W; c0 += kRowThreads) {
-            const int c = c0 + threadIdx.x;
-            const int r = (c < W) ? row[c] : -1;
-            const bool is_cand = r >= 0;
-            const uint64_t ballot = __ballot(is_cand);
-            const int prefix = __popcll(ballot & ((1ull << lane) - 1));
-            if (lane == 0) s_wave_count[wave] = __popcll(ballot);
-            __syncthreads();
-            int off = n, total = 0;
-            for (int w = 0; w < kRowThreads / 64; ++w) {
-                if (w < wave) off += s_wave_count[w];
-                total += s_wave_count[w];
+        // 1. this row's candidates of the chunk: (column, nearest site row)
+        const int16_t* rrow = rc + (int64_t)i * pitch + base;
+        if (cnt == S) {
+            uint32_t w[S / 2];
+#pragma unroll
+            for (int v = 0; v < S / 8; ++v) {
+                const int4 x = reinterpret_cast<const int4*>(rrow)[v];
+                w[4 * v + 0] = (uint32_t)x.x;
+                w[4 * v + 1] = (uint32_t)x.y;
+                w[4 * v + 2] = (uint32_t)x.z;
+                w[4 * v + 3] = (uint32_t)x.w;
             }
-            if (is_cand) cand[off + prefix] = ((uint32_t)c << 16) | (uint32_t)r;
-            n += total;
+#pragma unroll
+            for (int u = 0; u < S; ++u)
+                sl.c(base + u) = colhi[u] | ((w[u >> 1] >> (16 * (u & 1))) & 0xFFFFu);
+        } else {
+#pragma unroll
+            for (int u = 0; u < S; ++u)
+                if (u < cnt) sl.c(base + u) = colhi[u] | (uint32_t)(uint16_t)rrow[u];
+        }
+        // 2. envelope of the chunk: left-to-right scan, stack in place
+        int m = 0;
+        for (int u = 0; u < cnt; ++u) {
+            const uint32_t C = sl.c(base + u);
+            bool keep = true;
+            while (m > 0) {
+                const uint32_t A = sl.c(base + m - 1);
+                if (beats(C, A, i, sl.s(base + m - 1))) {  // C hides the stack top
+                    --m;
+                    continue;
+                }
+                keep = beats(C, A, i, W - 1);  // C wins somewhere inside the row
+                if (keep) sl.s(base + m) = (int16_t)first_win(A, C, i, W);
+                break;
+            }
+            if (m == 0) {
+                sl.s(base) = 0;
+                sl.c(base) = C;
+                m = 1;
+            } else if (keep) {
+                sl.c(base + m) = C;
+                ++m;
+            }
+        }
+        s_lo[t] = (int16_t)base;
+        s_hi[t] = (int16_t)(base + m);
+        s_nxt[t] = -1;
+        s_prv[t] = -1;
+        s_gf[t] = (int16_t)(m > 0 ? t : -1);
+        s_gl[t] = (int16_t)(m > 0 ? t : -1);
+        __syncthreads();
+        // 3. merge up the tree
+        for (int w = 1; w < nchunks; w <<= 1) {
+            if ((t & (2 * w - 1)) == 0 && t + w < nchunks)
+                merge_groups<T, S>(t, t + w, sl, s_lo, s_hi, s_nxt, s_prv, s_gf, s_gl, i, W);
             __syncthreads();
         }
-        // 2. Lower envelope, one scan over the candidates with a stack kept in
-        //    place at the front of the candidate list.
-        if (threadIdx.x == 0) {
-            int m = 0;
-            for (int q = 0; q < n; ++q) {
-                const uint32_t cq = cand[q];
-                const int l = (int)(cq >> 16), rl = (int)(cq & 0xFFFF);
-                int s = 0;
-                while (m > 0) {
-                    const uint32_t ct = cand[m - 1];
-                    s = first_win((int)(ct >> 16), (int)(ct & 0xFFFF), l, rl, i, W);
-                    if (s <= start[m - 1])
-                        --m;  // the new parabola hides the one on top
-                    else
-                        break;
-                }
-                if (m == 0) {
-                    cand[0] = cq;
-                    start[0] = 0;
-                    m = 1;
-                } else if (s <= W - 1) {
-                    cand[m] = cq;
-                    start[m] = (int16_t)s;
-                    ++m;
-                }
+        // 4. survivors to the front of the list, in column order (plain layout)
+        const int lo = s_lo[t];
+        const int c = s_hi[t] - lo;
+        uint32_t kc[S];
+        int16_t ks[S];
+#pragma unroll
+        for (int u = 0; u < S; ++u) {
+            if (u < c) {
+                kc[u] = sl.c(lo + u);
+                ks[u] = sl.s(lo + u);
             }
-            s_m = m;
+        }
+        int incl = c;
+#pragma unroll
+        for (int d = 1; d < 64; d <<= 1) {
+            const int v = __shfl_up(incl, d, 64);
+            if (lane >= d) incl += v;
+        }
+        if (lane == 63) s_wsum[wave] = incl;
+        __syncthreads();
+        int pos = incl - c, M = 0;
+#pragma unroll
+        for (int q = 0; q < NW; ++q) {
+            if (q < wave) pos += s_wsum[q];
+            M += s_wsum[q];
+        }
+#pragma unroll
+        for (int u = 0; u < S; ++u) {
+            if (u < c) {
+                cand[pos + u] = kc[u];
+                st[pos + u] = ks[u];
+            }
         }
         __syncthreads();
-        const int m = s_m;
-        // 3. Fill: each thread owns a contiguous run of pixels, finds the
-        //    parabola owning its first pixel by binary search and walks on.
-        const int seg = (W + kRowThreads - 1) / kRowThreads;
-        const int j0 = threadIdx.x * seg;
-        const int j1 = min(W, j0 + seg);
+        // 5. fill, four adjacent pixels per lane and step
         int32_t* drow = dist ? dist + (int64_t)i * out_pitch : nullptr;
         int32_t* frow = feat ? feat + (int64_t)i * out_pitch : nullptr;
-        if (m == 0) {
-            for (int j = j0; j < j1; ++j) {
-                if (drow) drow[j] = INT32_MAX;
-                if (frow) frow[j] = -1;
-            }
-        } else if (j0 < j1) {
-            int lo = 0, hi = m - 1;
-            while (lo < hi) {
-                const int mid = (lo + hi + 1) >> 1;
-                if (start[mid] <= j0) lo = mid; else hi = mid - 1;
-            }
-            int e = lo;
-            uint32_t ce = cand[e];
-            int k = (int)(ce >> 16), r = (int)(ce & 0xFFFF);
-            uint32_t dv = (uint32_t)((i - r) * (i - r));
-            int next = (e + 1 < m) ? start[e + 1] : W;
-            for (int j = j0; j < j1; ++j) {
-                while (j >= next) {
-                    ++e;
-                    ce = cand[e];
-                    k = (int)(ce >> 16);
-                    r = (int)(ce & 0xFFFF);
-                    dv = (uint32_t)((i - r) * (i - r));
-                    next = (e + 1 < m) ? start[e + 1] : W;
+        int e = 0;
+        for (int j = 4 * t; j < W; j += 4 * T) {
+            int d[4], f[4];
+            if (M == 0) {
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    d[v] = INT32_MAX;
+                    f[v] = -1;
                 }
-                if (drow) drow[j] = (int32_t)(dv + (uint32_t)((j - k) * (j - k)));
-                if (frow) frow[j] = r * W + k;
+            } else {
+                e = last_le(st, e, M, j);
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int jj = j + v;
+                    if (jj < W) {
+                        // the owner of jj: last survivor starting at or before jj
+                        while (e + 1 < M && st[e + 1] <= jj) ++e;
+                        const uint32_t C = cand[e];
+                        d[v] = parab(C, i, jj);
+                        f[v] = crow(C) * W + ccol(C);
+                    } else {
+                        d[v] = 0;
+                        f[v] = 0;
+                    }
+                }
             }
+            if (drow) store4(drow, j, W, vec, d[0], d[1], d[2], d[3]);
+            if (frow) store4(frow, j, W, vec, f[0], f[1], f[2], f[3]);
         }
-        __syncthreads();  // the next row reuses the candidate list
+        __syncthreads();  // the next row reuses the list and the chunk tables
     }
+}
+
+template <int T, int S, bool kSparse, bool kGlobal>
+hipError_t launch_form(int H, int W, const int16_t* rc, const int16_t* cols,
+                       const int32_t* meta, int32_t* dist, int32_t* feat, int64_t out_pitch,
+                       int vec, uint8_t* slots, hipStream_t stream) {
+    static int per_cu = 0;
+    if (per_cu == 0) {
+        int nb = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                &nb, k_row_envelope<T, S, kSparse, kGlobal>, T, 0) != hipSuccess || nb < 1)
+            nb = 1;
+        per_cu = nb;
+    }
+    int cus = 256;
+    int dev = 0;
+    if (hipGetDevice(&dev) == hipSuccess) {
+        int v = 0;
+        if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess &&
+            v > 0)
+            cus = v;
+    }
+    int grid = per_cu * cus;
+    if (kGlobal && grid > kWideSlots) grid = kWideSlots;
+    if (grid > H) grid = H;
+    const char* name = kSparse ? "k_row_sparse" : (kGlobal ? "k_row_dense_global" : "k_row_dense");
+    EDT_LAUNCH_AS(name, (k_row_envelope<T, S, kSparse, kGlobal>), dim3(grid), dim3(T), 0, stream,
+                  rc, cols, meta, H, W, dist, feat, out_pitch, vec, slots);
+    return hipGetLastError();
 }
 
 }  // namespace
 
-hipError_t launch_row_pass(const int16_t* rstar, int H, int W, int32_t* dist,
-                           int32_t* feat, int64_t out_pitch, uint8_t* ws,
-                           const Layout& L, hipStream_t stream) {
-    const bool wide = W > kRowLdsMaxW;
-    const size_t lds = wide ? 0 : align_up((size_t)W * 6, 16);
-    uint8_t* scratch = wide ? ws + L.rowscratch : nullptr;
-    const int grid = H < kRowSlots ? H : kRowSlots;
-    EDT_LAUNCH(k_row_envelope, dim3(grid), dim3(kRowThreads), lds, stream,
-                       rstar, H, W, dist, feat, out_pitch, scratch);
-    return hipGetLastError();
+hipError_t launch_row_pass(int H, int W, int32_t* dist, int32_t* feat, int64_t out_pitch,
+                           uint8_t* ws, const Layout& L, hipStream_t stream) {
+    const int16_t* rc = reinterpret_cast<const int16_t*>(ws + L.rc);
+    const int16_t* cols = reinterpret_cast<const int16_t*>(ws + L.cols);
+    const int32_t* meta = reinterpret_cast<const int32_t*>(ws + L.meta);
+    uint8_t* slots = ws + L.slots;
+    const bool a16 = (!dist || reinterpret_cast<uintptr_t>(dist) % 16 == 0) &&
+                     (!feat || reinterpret_cast<uintptr_t>(feat) % 16 == 0);
+    const int vec = a16 && (out_pitch % 4 == 0);
+    // Both forms are enqueued; each returns at once unless the image's number
+    // of candidate columns (known only on the device) is in its range.
+    hipError_t e = launch_form<kSparseLanes, kRowS, true, false>(H, W, rc, cols, meta, dist,
+                                                                 feat, out_pitch, vec, slots,
+                                                                 stream);
+    if (e != hipSuccess || W <= kSparseMaxN) return e;
+    if (W <= 2048)
+        return launch_form<128, kRowS, false, false>(H, W, rc, cols, meta, dist, feat,
+                                                     out_pitch, vec, slots, stream);
+    if (W <= 4096)
+        return launch_form<256, kRowS, false, false>(H, W, rc, cols, meta, dist, feat,
+                                                     out_pitch, vec, slots, stream);
+    if (W <= 8192)
+        return launch_form<512, kRowS, false, false>(H, W, rc, cols, meta, dist, feat,
+                                                     out_pitch, vec, slots, stream);
+    if (W <= kLdsMaxW)
+        return launch_form<1024, kRowS, false, false>(H, W, rc, cols, meta, dist, feat,
+                                                      out_pitch, vec, slots, stream);
+    return launch_form<1024, 2 * kRowS, false, true>(H, W, rc, cols, meta, dist, feat,
+                                                     out_pitch, vec, slots, stream);
 }
 
 }  // namespace edt

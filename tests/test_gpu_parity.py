@@ -149,3 +149,23 @@ def test_sqrt_epilogue_matches_oracle(edt):
     torch.cuda.synchronize()
     assert np.array_equal(d.cpu().numpy(), oracle.sqrt_f32(D))
     assert np.array_equal(d2.cpu().numpy(), oracle.sqrt_f32(big.cpu().numpy()))
+
+
+@pytest.mark.parametrize("W", [1025, 2048, 2049, 4096, 4097, 8192, 8193, 16384, 16385, 32767])
+def test_dense_row_forms_by_width(edt, W):
+    # every width class of the dense row pass (and the global-slot form)
+    H = 33 if W > 16384 else 70
+    m = workloads.bernoulli(H, W, 0.2, seed=W)
+    check_exact(edt, m, 0)
+    check_exact(edt, m, 1)
+
+
+@pytest.mark.parametrize("ncols", [1, 2, 63, 64, 65, 1023, 1024, 1025, 1100])
+def test_candidate_count_around_the_sparse_limit(edt, ncols):
+    # exactly ncols columns hold sites: the sparse form takes up to 1024
+    rng = np.random.default_rng(ncols)
+    H, W = 90, 3000
+    m = np.zeros((H, W), np.uint8)
+    cols = rng.choice(W, size=ncols, replace=False)
+    m[rng.integers(0, H, size=ncols), cols] = 1
+    check_exact(edt, m, 0)
