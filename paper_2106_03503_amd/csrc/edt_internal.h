@@ -45,7 +45,7 @@ struct Layout {
     size_t bits;       // uint64 [nb][W]  site bits of each band column
     size_t up;         // int16  [nb][W]  last site row above the band (-1: none)
     size_t down;       // int16  [nb][W]  first site row below the band (kNoBelow: none)
-    size_t flag;       // int32  [W]      column holds a site
+    size_t flag;       // uint8  [cand_pitch(W)]  column holds a site (0 past W)
     size_t cols;       // int16  [cand_pitch(W)]  columns holding a site, increasing
     size_t meta;       // int32  [4]      {n = number of such columns, rc row pitch}
     size_t rc;         // int16  [H][cand_pitch(W)] nearest site row of each listed column
@@ -65,7 +65,7 @@ inline Layout layout_for(int H, int W) {
     L.down = off;
     off = align_up(off + (size_t)L.nb * W * 2, 256);
     L.flag = off;
-    off = align_up(off + (size_t)W * 4, 256);
+    off = align_up(off + cp, 256);
     L.cols = off;
     off = align_up(off + cp * 2, 256);
     L.meta = off;

@@ -168,15 +168,31 @@ __device__ __forceinline__ int last_le(const int16_t* __restrict__ st, int lo, i
     return a;
 }
 
+// Last index in [e, M) with st[idx] <= j, given st[e] <= j: gallop forward
+// from e, then bisect the last stride (O(1) when the owner is unchanged).
+__device__ __forceinline__ int advance(const int16_t* __restrict__ st, int e, int M, int j) {
+    int step = 1;
+    while (e + step < M && st[e + step] <= j) {
+        e += step;
+        step <<= 1;
+    }
+    return last_le(st, e, min(M, e + step), j);
+}
+
+typedef int v4i __attribute__((ext_vector_type(4)));
+
+// Four output pixels; the outputs are written once and not read back by this
+// library, so they are stored non-temporally (streamed past the caches).
 __device__ __forceinline__ void store4(int32_t* __restrict__ p, int j, int W, bool vec,
                                        int v0, int v1, int v2, int v3) {
     if (vec && j + 4 <= W) {
-        *reinterpret_cast<int4*>(p + j) = make_int4(v0, v1, v2, v3);
+        const v4i v = {v0, v1, v2, v3};
+        __builtin_nontemporal_store(v, reinterpret_cast<v4i*>(p + j));
     } else {
-        p[j] = v0;
-        if (j + 1 < W) p[j + 1] = v1;
-        if (j + 2 < W) p[j + 2] = v2;
-        if (j + 3 < W) p[j + 3] = v3;
+        __builtin_nontemporal_store(v0, p + j);
+        if (j + 1 < W) __builtin_nontemporal_store(v1, p + j + 1);
+        if (j + 2 < W) __builtin_nontemporal_store(v2, p + j + 2);
+        if (j + 3 < W) __builtin_nontemporal_store(v3, p + j + 3);
     }
 }
 
@@ -329,14 +345,20 @@ __global__ __launch_bounds__(T) void k_row_envelope(
                     f[v] = -1;
                 }
             } else {
-                e = last_le(st, e, M, j);
+                // owner of pixel j: the last survivor starting at or before j,
+                // searched forward from this lane's previous owner
+                e = advance(st, e, M, j);
+                uint32_t C = cand[e];
+                int nst = e + 1 < M ? st[e + 1] : INT32_MAX;
 #pragma unroll
                 for (int v = 0; v < 4; ++v) {
                     const int jj = j + v;
                     if (jj < W) {
-                        // the owner of jj: last survivor starting at or before jj
-                        while (e + 1 < M && st[e + 1] <= jj) ++e;
-                        const uint32_t C = cand[e];
+                        while (jj >= nst) {
+                            ++e;
+                            C = cand[e];
+                            nst = e + 1 < M ? st[e + 1] : INT32_MAX;
+                        }
                         d[v] = parab(C, i, jj);
                         f[v] = crow(C) * W + ccol(C);
                     } else {

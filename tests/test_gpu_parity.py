@@ -169,3 +169,14 @@ def test_candidate_count_around_the_sparse_limit(edt, ncols):
     cols = rng.choice(W, size=ncols, replace=False)
     m[rng.integers(0, H, size=ncols), cols] = 1
     check_exact(edt, m, 0)
+
+
+@pytest.mark.parametrize("W,pad", [(1029, 11), (1029, 3), (1029, 0), (1024, 0), (1040, 0),
+                                   (1036, 0), (17, 15), (33, 0)])
+def test_mask_load_paths(edt, W, pad):
+    # mask row pitch = W + pad bytes: multiples of 16 and of 4 take the wide
+    # and word loads, others the byte loads; widths not a multiple of the
+    # lane's column count leave a ragged last lane
+    m = workloads.bernoulli(131, W, 0.01, seed=W + pad)
+    check_exact(edt, m, 0, pitch_pad=pad)
+    check_exact(edt, m, 1, pitch_pad=pad)
