@@ -1,18 +1,25 @@
 #!/usr/bin/env python3
 """Throughput of the exact squared EDT + feature transform on one MI355X.
 
-One step = one edt_feature call (site predicate, vertical pass, lower envelope
-and fill: squared distance and nearest-site index for every pixel) on one
-synthetic image already resident in HBM.  The default workload is the
-16384 x 16384 image with 30 random object points, the single-image size at
-which the HBM roofline is measured.
-
-Prints ONE JSON line (see the keys below).  --gpus N > 1 is refused: this
-build runs on one GPU.
+Workloads (--workload):
+  points16k (default)  one step = one edt_feature call on a 16384 x 16384 image
+                       with 30 random object points: the single-image size at
+                       which the HBM roofline is measured;
+  disks4k, disks4k_inside, bernoulli256
+                       other single images (4096^2 disks outside / inside,
+                       256^2 Bernoulli(0.01));
+  batch2048            one step = one edt_batch_submit over 2048 images of
+                       uneven size (sides 64..1024, 5-60 ellipses, mixed
+                       polarity), replayed as a captured graph; the same
+                       images launched one by one through edt_feature are
+                       timed beside it ("per_image").
+Inputs are resident in HBM before the timed region.  Prints ONE JSON line.
+--gpus N > 1 is refused: this build runs on one GPU.
 """
 from __future__ import annotations
 
 import argparse
+import ctypes
 import hashlib
 import json
 import os
@@ -24,21 +31,20 @@ sys.path.insert(0, ROOT)
 
 METRIC = "Gpixel/s exact sq-EDT+feature transform and % HBM roofline; batched vs per-image"
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published peak
-
 PATH_BYTES_PER_PX = 13.0  # 1 mask + 2 + 2 intermediate + 4 D + 4 F
 
 
 def algo_bytes(kernel: str, H: int, W: int, n: int, with_dist: bool = True) -> int:
     """Algorithmic HBM bytes of one launch of `kernel` on an H x W image whose
     sites occupy n columns: what the kernel must read and write at minimum
-    given its inputs and outputs ('Roofline')."""
+    given its inputs and outputs ('Measurement')."""
     nb = (H + 63) // 64
     if kernel == "k_band_bits":          # mask in, one site bit per pixel out
         return H * W + nb * W * 8
     if kernel == "k_band_carry":         # site bits in, two int16 carries per band out
-        return nb * W * 8 + nb * W * 4 + W * 4
+        return nb * W * 8 + nb * W * 4 + W
     if kernel == "k_col_compact":        # column flags in, column list out
-        return W * 4 + n * 2
+        return W + n * 2
     if kernel == "k_nearest_row":        # bits + carries of listed columns in, int16 rows out
         return nb * n * 12 + H * n * 2
     if kernel.startswith("k_row_"):      # int16 rows in, int32 D and F out
@@ -52,7 +58,8 @@ def site_columns(mask, polarity) -> int:
     site = (mask != 0) if polarity == 0 else (mask == 0)
     return int(np.count_nonzero(site.any(axis=0)))
 
-WORKLOADS = {
+
+SINGLE = {
     "points16k": dict(
         H=16384, W=16384, polarity=0,
         desc="16384x16384 uint8 mask, 30 uniform random object points (Voronoi-style); "
@@ -69,6 +76,9 @@ WORKLOADS = {
         H=256, W=256, polarity=0,
         desc="256x256 uint8 mask, Bernoulli(0.01) object pixels"),
 }
+BATCH_DESC = ("2048 uint8 masks of uneven size (H, W uniform in 64..1024), 5-60 overlapping "
+              "random ellipses each (semi-axes 4-80), polarity Bernoulli(0.5); int32 squared "
+              "distance + int32 nearest-site index per pixel")
 
 
 def make_mask(name):
@@ -106,17 +116,25 @@ def traffic_from_profiles(kernel: str, workload: str):
     return ent.get("bytes_per_launch")
 
 
-def cpu_baseline(mask, polarity, units_px):
+def cpu_threads() -> int:
     import oracle
-    threads = oracle.default_threads()
+    return oracle.default_threads()
+
+
+def cpu_baseline(images, units_px):
+    """The oracle's separable transform over the images, on the host cores."""
+    import oracle
+    threads = cpu_threads()
     t0 = time.perf_counter()
-    oracle.separable(mask, polarity, nthreads=threads)
+    for m, pol in images:
+        oracle.separable(m, pol, nthreads=threads)
     dt = time.perf_counter() - t0
+    what = (f"the whole {images[0][0].shape[0]}x{images[0][0].shape[1]} image" if len(images) == 1
+            else f"all {len(images)} images of the batch, one after the other")
     return {"value": round(units_px / dt / 1e9, 5), "unit": "Gpixel/s", "cores": threads,
             "kind": "oracle",
-            "sample": f"one full pass of the oracle's separable transform (vertical pass + "
-                      f"lower envelope + fill) over the whole {mask.shape[0]}x{mask.shape[1]} "
-                      f"image, {threads} POSIX threads, {dt:.2f} s"}
+            "sample": f"one full pass of the oracle's separable transform (vertical pass + lower "
+                      f"envelope + fill) over {what}, {threads} POSIX threads, {dt:.2f} s"}
 
 
 def copy_calibration(steps):
@@ -132,31 +150,53 @@ def copy_calibration(steps):
     print(json.dumps({"copy_bytes": n, "launches": steps}))
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=50)
-    ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", default="points16k", choices=sorted(WORKLOADS))
-    ap.add_argument("--no-cpu", action="store_true", help="skip the cpu_baseline leg")
-    ap.add_argument("--copy-calibration", action="store_true")
-    args = ap.parse_args()
-
-    if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
-              "(see DESIGN.md, 'More than one GPU').", file=sys.stderr)
-        sys.exit(2)
-
+def timed(step, steps, warmup, profile=True):
+    """Warm up, then time `steps` calls between two device synchronisations;
+    returns (ms per step, per-kernel {name: (launches, total ms)})."""
     import torch
     import paper_2106_03503_amd as edt
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    if profile:
+        edt.profile_begin()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    kt = edt.profile_end() if profile else {}
+    return (t1 - t0) * 1e3 / steps, kt
 
-    if args.copy_calibration:
-        copy_calibration(args.steps)
-        return
 
-    wl = WORKLOADS[args.workload]
+def roofline(kt, algo_per_launch, workload):
+    dom = max(kt, key=lambda k: kt[k][1])
+    launches, total_ms = kt[dom]
+    avg_ms = total_ms / launches
+    algo = algo_per_launch(dom)
+    achieved = algo / (avg_ms * 1e-3) / 1e9
+    return {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1),
+            "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": traffic_from_profiles(dom, workload),
+            "algorithmic_bytes_per_launch": int(algo), "avg_launch_ms": round(avg_ms, 4)}
+
+
+def base_line(args, value, ms, config):
+    return {
+        "metric": METRIC, "value": round(value, 3), "unit": "Gpixel/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "int32",
+        "data": "synthetic", "config": config,
+    }
+
+
+def run_single(args):
+    import torch
+    import paper_2106_03503_amd as edt
+    wl = SINGLE[args.workload]
     H, W, pol = wl["H"], wl["W"], wl["polarity"]
     mask_np = make_mask(args.workload)
+    n = site_columns(mask_np, pol)
     dev = torch.device("cuda:0")
     mask = torch.from_numpy(mask_np).to(dev)
     D = torch.empty((H, W), dtype=torch.int32, device=dev)
@@ -167,57 +207,97 @@ def main():
     def step():
         edt.feature(mask, polarity=pol, out_dist=D, out_feat=F, workspace=ws, stream=stream)
 
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    edt.profile_begin()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        step()
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    kt = edt.profile_end()
-    ms_per_step = (t1 - t0) * 1e3 / args.steps
+    ms, kt = timed(step, args.steps, args.warmup)
     px = H * W
-    value = px / (ms_per_step * 1e-3) / 1e9
-
-    # dominant kernel and its roofline
-    dom = max(kt, key=lambda k: kt[k][1])
-    launches, total_ms = kt[dom]
-    avg_ms = total_ms / launches
-    algo = algo_bytes(dom, H, W, site_columns(mask_np, pol))
-    achieved = algo / (avg_ms * 1e-3) / 1e9
-    traffic = traffic_from_profiles(dom, args.workload)
-    roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1),
-                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": traffic, "algorithmic_bytes_per_launch": int(algo),
-                "avg_launch_ms": round(avg_ms, 4)}
-
-    out = {
-        "metric": METRIC,
-        "value": round(value, 3),
-        "unit": "Gpixel/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": round(ms_per_step, 4),
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "int32",
-        "data": "synthetic",
-        "config": {"workload": wl["desc"], "H": H, "W": W, "polarity": pol,
-                   "call": "edt_feature", "parallelism": "single GPU"},
-        "roofline": roofline,
-        "path_hbm": {"bytes_per_px": PATH_BYTES_PER_PX,
-                     "achieved_GBs": round(PATH_BYTES_PER_PX * px / (ms_per_step * 1e-3) / 1e9, 1),
-                     "frac": round(PATH_BYTES_PER_PX * px / (ms_per_step * 1e-3) / 1e9
-                                   / HBM_PEAK_GBS, 4)},
-        "kernels_ms_per_step": {k: round(v[1] / max(1, v[0]) * v[0] / args.steps, 4)
-                                for k, v in sorted(kt.items())},
-    }
+    out = base_line(args, px / (ms * 1e-3) / 1e9, ms,
+                    {"workload": wl["desc"], "H": H, "W": W, "polarity": pol,
+                     "call": "edt_feature", "parallelism": "single GPU"})
+    out["roofline"] = roofline(kt, lambda k: algo_bytes(k, H, W, n), args.workload)
+    gbs = PATH_BYTES_PER_PX * px / (ms * 1e-3) / 1e9
+    out["path_hbm"] = {"bytes_per_px": PATH_BYTES_PER_PX, "achieved_GBs": round(gbs, 1),
+                       "frac": round(gbs / HBM_PEAK_GBS, 4)}
+    out["kernels_ms_per_step"] = {k: round(v[1] / args.steps, 4) for k, v in sorted(kt.items())}
     if not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(mask_np, pol, px)
+        out["cpu_baseline"] = cpu_baseline([(mask_np, pol)], px)
+    return out
+
+
+def run_batch(args):
+    import numpy as np
+    import torch
+    import paper_2106_03503_amd as edt
+    from paper_2106_03503_amd import _lib
+    import workloads
+    imgs = workloads.ragged_batch(2048)
+    dev = torch.device("cuda:0")
+    plan = edt.BatchPlan([(m.shape[0], m.shape[1], p, True) for m, p in imgs])
+    mask = plan.pack([m for m, _ in imgs], dev)
+    D, F = plan.outputs(dev)
+    ws = torch.empty(max(plan.workspace_bytes, 1), dtype=torch.uint8, device=dev)
+    stream = torch.cuda.current_stream()
+    px = sum(m.size for m, _ in imgs)
+
+    def step():
+        plan.submit(mask, D, F, workspace=ws, stream=stream)
+
+    ms, _ = timed(step, args.steps, args.warmup, profile=False)      # graph replays
+    ms_prof, kt = timed(step, max(3, args.steps // 4), 1, profile=True)  # per-kernel times
+
+    # the same images, one edt_feature call each (plain per-image launches)
+    wsz = max(edt.workspace_bytes(m.shape[0], m.shape[1]) for m, _ in imgs)
+    ws1 = torch.empty(wsz, dtype=torch.uint8, device=dev)
+    calls = []
+    for q, (m, pol) in enumerate(imgs):
+        h, w = m.shape
+        calls.append((mask.data_ptr() + plan.mask_off[q], h, w, plan.mask_pitch[q], pol, 0,
+                      D.data_ptr() + 4 * plan.out_off[q], F.data_ptr() + 4 * plan.out_off[q],
+                      plan.out_pitch[q], ws1.data_ptr(), wsz, stream.cuda_stream))
+    fn = _lib.lib.edt_feature
+
+    def per_image():
+        for c in calls:
+            if fn(*c) != 0:
+                raise RuntimeError("edt_feature failed")
+
+    ms_single, _ = timed(per_image, max(2, args.steps // 5), 1, profile=False)
+
+    ns = [site_columns(m, p) for m, p in imgs]
+    out = base_line(args, px / (ms * 1e-3) / 1e9, ms,
+                    {"workload": BATCH_DESC, "images": len(imgs), "pixels": int(px),
+                     "call": "edt_batch_submit (graph replay)", "parallelism": "single GPU"})
+    out["roofline"] = roofline(
+        kt, lambda k: sum(algo_bytes(k, m.shape[0], m.shape[1], n) for (m, _), n in zip(imgs, ns)),
+        args.workload)
+    out["per_image"] = {"value": round(px / (ms_single * 1e-3) / 1e9, 3),
+                        "ms_per_step": round(ms_single, 4), "call": "edt_feature per image"}
+    out["batched_over_per_image"] = round(ms_single / ms, 2)
+    out["kernels_ms_per_step"] = {k: round(v[1] / max(3, args.steps // 4), 4)
+                                  for k, v in sorted(kt.items())}
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(imgs, px)
+    plan.close()
+    return out
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", default="points16k",
+                    choices=sorted(list(SINGLE) + ["batch2048"]))
+    ap.add_argument("--no-cpu", action="store_true", help="skip the cpu_baseline leg")
+    ap.add_argument("--copy-calibration", action="store_true")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
+              "(see DESIGN.md, 'More than one GPU').", file=sys.stderr)
+        sys.exit(2)
+    if args.copy_calibration:
+        copy_calibration(args.steps)
+        return
+    out = run_batch(args) if args.workload == "batch2048" else run_single(args)
     print(json.dumps(out), flush=True)
 
 

@@ -54,7 +54,9 @@ typedef int32_t edt_status;
 #define EDT_ERR_INVALID_ARG (-1)   /* null pointer, bad pitch, bad enum, short workspace */
 #define EDT_ERR_UNSUPPORTED (-2)   /* a metric this build does not provide */
 #define EDT_ERR_TOO_LARGE (-3)     /* H or W outside [1, EDT_MAX_SIDE] */
-#define EDT_ERR_OUT_OF_MEMORY (-4) /* a host-side allocation failed */
+#define EDT_ERR_OUT_OF_MEMORY (-4) /* a host or library-owned allocation failed */
+#define EDT_ERR_BUSY (-5)          /* a server's memory budget or queue is full */
+#define EDT_ERR_NOT_READY (-6)     /* a wait timed out; the work is still in flight */
 #define EDT_ERR_DEVICE (-7)        /* a HIP call or kernel launch failed */
 
 #define EDT_TO_OBJECT 0
@@ -108,6 +110,55 @@ edt_status edt_feature(const uint8_t *mask, int32_t H, int32_t W,
  * arrays of n elements (they may not overlap). */
 edt_status edt_sqrt_f32(const int32_t *dist_sq, float *dist, int64_t n,
                         void *stream);
+
+/* ---- batches of images of uneven size ----------------------------------- */
+
+/* One image of a batch.  Its mask starts mask_offset bytes after the batch's
+ * mask base (rows mask_pitch bytes apart); its outputs start out_offset
+ * elements after the batch's dist/feature bases (rows out_pitch elements
+ * apart).  Images may have different sizes and polarities; the feature index
+ * is local to the image (r*W + c). */
+typedef struct {
+    int64_t mask_offset;
+    int64_t mask_pitch;
+    int64_t out_offset;
+    int64_t out_pitch;
+    int32_t H, W;          /* 1 <= H <= EDT_MAX_SIDE, 1 <= W <= EDT_BATCH_MAX_W */
+    int32_t polarity;      /* EDT_TO_OBJECT or EDT_TO_BACKGROUND */
+    int32_t want_feature;  /* 0: this image's features are not written */
+} edt_image_desc;
+
+#define EDT_BATCH_MAX_W 16384  /* widest image of a batch */
+#define EDT_BATCH_MAX_IMAGES (1 << 20)
+
+typedef struct edt_plan edt_plan;
+
+/* Plan a batch of n images (host array `images`).  The same transform as
+ * edt_feature / edt_sq runs on every image; all images' phases run in one
+ * persistent launch per phase over a table of the images (owned by the plan,
+ * in device memory of the current device), and repeated submissions with the
+ * same buffers replay a captured HIP graph.  want_dist = 0: no distances are
+ * written (dist_base may then be NULL at submission).  *workspace_bytes (host)
+ * receives the device workspace the submissions need.  The plan is not safe
+ * for concurrent submissions from several threads.  Errors: EDT_ERR_TOO_LARGE
+ * (a side, or the total of rows or work items, out of range),
+ * EDT_ERR_INVALID_ARG, EDT_ERR_OUT_OF_MEMORY, EDT_ERR_DEVICE. */
+edt_status edt_batch_plan(const edt_image_desc *images, int32_t n, int32_t want_dist,
+                          edt_plan **plan, size_t *workspace_bytes);
+
+/* Enqueue the batch on stream.  mask_base, dist_base, feat_base and workspace
+ * are device pointers (feat_base may be NULL when no image wants features,
+ * dist_base when the plan has want_dist = 0); the workspace is 256-byte
+ * aligned, at least the planned size, and must not be shared with work that
+ * may overlap.  Results are bit-identical to edt_feature / edt_sq on each
+ * image alone. */
+edt_status edt_batch_submit(edt_plan *plan, const uint8_t *mask_base, int32_t *dist_base,
+                            int32_t *feat_base, void *workspace, size_t workspace_bytes,
+                            void *stream);
+
+/* Release a plan (its device table and graphs).  Work already enqueued with
+ * it must have completed. */
+edt_status edt_plan_destroy(edt_plan *plan);
 
 /* ---- kernel timing (observability) ------------------------------------ */
 

@@ -15,6 +15,7 @@ from ._lib import (  # noqa: F401
     EDT_NO_SITE,
     EDT_TO_BACKGROUND,
     EDT_TO_OBJECT,
+    BatchPlan,
     EDTError,
     abi_version,
     feature,

@@ -184,3 +184,105 @@ def profile_end() -> dict:
            "edt_profile_end")
     return {arr[q].name.decode(): (int(arr[q].launches), float(arr[q].total_ms))
             for q in range(min(n.value, cap))}
+
+
+# ---------------------------------------------------------------- batches
+
+class ImageDesc(ctypes.Structure):
+    _fields_ = [("mask_offset", ctypes.c_int64), ("mask_pitch", ctypes.c_int64),
+                ("out_offset", ctypes.c_int64), ("out_pitch", ctypes.c_int64),
+                ("H", ctypes.c_int32), ("W", ctypes.c_int32),
+                ("polarity", ctypes.c_int32), ("want_feature", ctypes.c_int32)]
+
+
+def _bind_batch():
+    P, i32, sz = ctypes.c_void_p, ctypes.c_int32, ctypes.c_size_t
+    _lib.edt_batch_plan.argtypes = [P, i32, i32, P, P]
+    _lib.edt_batch_plan.restype = i32
+    _lib.edt_batch_submit.argtypes = [P, P, P, P, P, sz, P]
+    _lib.edt_batch_submit.restype = i32
+    _lib.edt_plan_destroy.argtypes = [P]
+    _lib.edt_plan_destroy.restype = i32
+
+
+_bind_batch()
+
+
+def _round_up(v: int, a: int) -> int:
+    return (v + a - 1) // a * a
+
+
+class BatchPlan:
+    """A batch of images of uneven size laid out back to back in one mask
+    buffer (rows padded to 16 bytes) and one buffer per output (rows padded to
+    4 elements).  ``images`` is a list of (H, W, polarity, want_feature)."""
+
+    def __init__(self, images, want_dist: bool = True):
+        self.images = [(int(h), int(w), int(p), bool(f)) for h, w, p, f in images]
+        n = len(self.images)
+        descs = (ImageDesc * max(n, 1))()
+        moff = ooff = 0
+        self.mask_off, self.out_off, self.mask_pitch, self.out_pitch = [], [], [], []
+        for q, (h, w, p, f) in enumerate(self.images):
+            mp, op = _round_up(w, 16), _round_up(w, 4)
+            descs[q] = ImageDesc(moff, mp, ooff, op, h, w, p, int(f))
+            self.mask_off.append(moff)
+            self.out_off.append(ooff)
+            self.mask_pitch.append(mp)
+            self.out_pitch.append(op)
+            moff += h * mp
+            ooff += h * op
+        self.mask_bytes, self.out_elems = moff, ooff
+        self.want_dist = bool(want_dist)
+        self.any_feat = any(f for _, _, _, f in self.images)
+        self._plan = ctypes.c_void_p()
+        ws = ctypes.c_size_t(0)
+        _check(_lib.edt_batch_plan(ctypes.cast(descs, ctypes.c_void_p), n, int(want_dist),
+                                   ctypes.byref(self._plan), ctypes.byref(ws)), "edt_batch_plan")
+        self.workspace_bytes = int(ws.value)
+
+    def pack(self, masks, device) -> torch.Tensor:
+        """Copy a list of 2-D uint8 numpy masks into one device buffer."""
+        import numpy as np
+        flat = np.zeros(self.mask_bytes, np.uint8)
+        for q, m in enumerate(masks):
+            h, w = self.images[q][:2]
+            if m.shape != (h, w):
+                raise ValueError(f"mask {q} has shape {m.shape}, planned {(h, w)}")
+            view = flat[self.mask_off[q]:self.mask_off[q] + h * self.mask_pitch[q]]
+            view.reshape(h, self.mask_pitch[q])[:, :w] = m
+        return torch.from_numpy(flat).to(device)
+
+    def outputs(self, device):
+        d = torch.empty(self.out_elems, dtype=torch.int32, device=device) if self.want_dist else None
+        f = torch.empty(self.out_elems, dtype=torch.int32, device=device) if self.any_feat else None
+        return d, f
+
+    def image(self, flat: torch.Tensor, q: int) -> torch.Tensor:
+        """(H, W) view of image q inside a flat output buffer."""
+        h, w = self.images[q][:2]
+        o, p = self.out_off[q], self.out_pitch[q]
+        return flat[o:o + h * p].view(h, p)[:, :w]
+
+    def submit(self, mask_flat, dist_flat=None, feat_flat=None, workspace=None, stream=None):
+        if workspace is None:
+            workspace = torch.empty(max(self.workspace_bytes, 1), dtype=torch.uint8,
+                                    device=mask_flat.device)
+        _check(_lib.edt_batch_submit(self._plan, mask_flat.data_ptr(),
+                                     dist_flat.data_ptr() if dist_flat is not None else None,
+                                     feat_flat.data_ptr() if feat_flat is not None else None,
+                                     workspace.data_ptr(),
+                                     workspace.numel() * workspace.element_size(),
+                                     _stream_ptr(stream)), "edt_batch_submit")
+        return workspace
+
+    def close(self):
+        if self._plan:
+            _check(_lib.edt_plan_destroy(self._plan), "edt_plan_destroy")
+            self._plan = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

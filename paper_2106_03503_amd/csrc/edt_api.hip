@@ -27,9 +27,8 @@ hipError_t launch_sqrt(const int32_t* D, float* out, int64_t n, hipStream_t stre
     return hipGetLastError();
 }
 
-static edt_status check_image(const uint8_t* mask, int32_t H, int32_t W,
-                              int64_t mask_pitch, int32_t polarity, int32_t metric,
-                              int64_t out_pitch) {
+edt_status check_image(const uint8_t* mask, int32_t H, int32_t W, int64_t mask_pitch,
+                       int32_t polarity, int32_t metric, int64_t out_pitch) {
     if (H < 1 || W < 1 || H > EDT_MAX_SIDE || W > EDT_MAX_SIDE) return EDT_ERR_TOO_LARGE;
     if (!mask || mask_pitch < W || out_pitch < W) return EDT_ERR_INVALID_ARG;
     if (polarity != EDT_TO_OBJECT && polarity != EDT_TO_BACKGROUND) return EDT_ERR_INVALID_ARG;
@@ -51,11 +50,18 @@ static edt_status run(const uint8_t* mask, int32_t H, int32_t W, int64_t mask_pi
     if (!workspace || workspace_bytes < L.total) return EDT_ERR_INVALID_ARG;
     if ((reinterpret_cast<uintptr_t>(workspace) & 255) != 0) return EDT_ERR_INVALID_ARG;
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-    uint8_t* ws = static_cast<uint8_t*>(workspace);
-    if (launch_column_pass(mask, H, W, mask_pitch, polarity, ws, L, s) != hipSuccess)
-        return EDT_ERR_DEVICE;
-    if (launch_row_pass(H, W, dist, feat, out_pitch, ws, L, s) != hipSuccess)
-        return EDT_ERR_DEVICE;
+    Img g;
+    g.mask = mask;
+    g.mpitch = mask_pitch;
+    g.dist = dist;
+    g.feat = feat;
+    g.opitch = out_pitch;
+    g.ws = static_cast<uint8_t*>(workspace);
+    g.H = H;
+    g.W = W;
+    g.pol = polarity;
+    if (launch_column_pass(g, s) != hipSuccess) return EDT_ERR_DEVICE;
+    if (launch_row_pass(g, g.ws + L.slots, s) != hipSuccess) return EDT_ERR_DEVICE;
     return EDT_OK;
 }
 
@@ -71,7 +77,9 @@ const char* edt_status_string(edt_status s) {
         case EDT_ERR_INVALID_ARG: return "invalid argument";
         case EDT_ERR_UNSUPPORTED: return "unsupported metric";
         case EDT_ERR_TOO_LARGE: return "image too large";
-        case EDT_ERR_OUT_OF_MEMORY: return "out of host memory";
+        case EDT_ERR_OUT_OF_MEMORY: return "out of memory";
+        case EDT_ERR_BUSY: return "busy";
+        case EDT_ERR_NOT_READY: return "not ready";
         case EDT_ERR_DEVICE: return "device error";
         default: return "unknown status";
     }

@@ -12,11 +12,15 @@ namespace edt {
 constexpr int kBand = 64;
 // "No site below" marker of the band carries (larger than any row index).
 constexpr int16_t kNoBelow = INT16_MAX;
+// Columns per workgroup of the band-bit pass (4 wavefronts x 64 lanes x 16).
+constexpr int kBitsCols = 1024;
 // Band carries: columns per workgroup and band slices (one wavefront each).
 constexpr int kCarryCols = 64;
 constexpr int kCarrySlices = 16;
+// Listed columns per work item of the nearest-row pass.
+constexpr int kNearCols = 256;
 
-// Row pass: candidate slots per lane (also pixels per lane in the dense fill).
+// Row pass: candidate slots per lane.
 constexpr int kRowS = 16;
 // One-wavefront row pass for rows with at most kSparseMaxN candidates.
 constexpr int kSparseLanes = 64;
@@ -25,19 +29,16 @@ constexpr int kSparseMaxN = kSparseLanes * kRowS;
 constexpr int kLdsMaxW = 1024 * kRowS;
 // Workgroups (and global-memory row slots) of the row pass for wider rows.
 constexpr int kWideSlots = 512;
+// Candidate capacity of one global row slot (1024 lanes x 2*kRowS slots).
+constexpr int kWideCap = 1024 * 2 * kRowS;
 
 __host__ __device__ inline size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
 // Candidate-list capacity per row (multiple of 32 so every lane's chunk of
 // 16 or 32 slots is whole).
 __host__ __device__ inline int cand_pitch(int W) { return (int)align_up((size_t)W, 32); }
-// Candidate capacity of one global row slot (1024 lanes x 2*kRowS slots),
-// used for rows wider than kLdsMaxW, and the slot's size in bytes
-// (4-byte candidates, then 2-byte starts).
-constexpr int kWideCap = 1024 * 2 * kRowS;
-__host__ __device__ inline size_t wide_slot_bytes(int /*W*/) {
-    return align_up((size_t)kWideCap * 6, 256);
-}
+// Bytes of one global row slot (4-byte candidates, then 2-byte starts).
+__host__ __device__ inline size_t wide_slot_bytes() { return align_up((size_t)kWideCap * 6, 256); }
 
 // Byte offsets of the pieces of one image's workspace.
 struct Layout {
@@ -49,11 +50,13 @@ struct Layout {
     size_t cols;       // int16  [cand_pitch(W)]  columns holding a site, increasing
     size_t meta;       // int32  [4]      {n = number of such columns, rc row pitch}
     size_t rc;         // int16  [H][cand_pitch(W)] nearest site row of each listed column
-    size_t slots;      // row slots for rows wider than kLdsMaxW
+    size_t slots;      // row slots for rows wider than kLdsMaxW (single images only)
     size_t total;
 };
 
-inline Layout layout_for(int H, int W) {
+// Workspace layout of one image; with_slots adds the global row slots that
+// the single-image row pass uses for rows wider than kLdsMaxW.
+__host__ __device__ inline Layout layout_for(int H, int W, bool with_slots = true) {
     Layout L;
     L.nb = (H + kBand - 1) / kBand;
     const size_t cp = (size_t)cand_pitch(W);
@@ -73,9 +76,107 @@ inline Layout layout_for(int H, int W) {
     L.rc = off;
     off = align_up(off + (size_t)H * cp * 2, 256);
     L.slots = off;
-    if (W > kLdsMaxW) off = align_up(off + (size_t)kWideSlots * wide_slot_bytes(W), 256);
+    if (with_slots && W > kLdsMaxW) off = align_up(off + (size_t)kWideSlots * wide_slot_bytes(), 256);
     L.total = off;
     return L;
+}
+
+// One image as the kernels see it.
+struct Img {
+    const uint8_t* mask;
+    int64_t mpitch;    // bytes between mask rows
+    int32_t* dist;     // may be null
+    int32_t* feat;     // may be null
+    int64_t opitch;    // elements between output rows
+    uint8_t* ws;       // this image's workspace (layout_for(H, W))
+    int H, W, pol;
+};
+
+// Pointers into an image's workspace.
+struct Views {
+    uint64_t* bits;
+    int16_t* up;
+    int16_t* down;
+    uint8_t* flag;
+    int16_t* cols;
+    int32_t* meta;
+    int16_t* rc;
+};
+
+__host__ __device__ inline Views views_of(const Img& g) {
+    const Layout L = layout_for(g.H, g.W, false);
+    Views v;
+    v.bits = reinterpret_cast<uint64_t*>(g.ws + L.bits);
+    v.up = reinterpret_cast<int16_t*>(g.ws + L.up);
+    v.down = reinterpret_cast<int16_t*>(g.ws + L.down);
+    v.flag = g.ws + L.flag;
+    v.cols = reinterpret_cast<int16_t*>(g.ws + L.cols);
+    v.meta = reinterpret_cast<int32_t*>(g.ws + L.meta);
+    v.rc = reinterpret_cast<int16_t*>(g.ws + L.rc);
+    return v;
+}
+
+// Work items of each phase for one image.
+__host__ __device__ inline int items_bits(int H, int W) {
+    return ((H + kBand - 1) / kBand) * ((W + kBitsCols - 1) / kBitsCols);
+}
+__host__ __device__ inline int items_carry(int, int W) { return (W + kCarryCols - 1) / kCarryCols; }
+__host__ __device__ inline int items_near(int H, int W) {
+    return ((H + kBand - 1) / kBand) * ((W + kNearCols - 1) / kNearCols);
+}
+
+// Phases of the transform, in launch order.
+enum Phase { kPhBits = 0, kPhCarry = 1, kPhCompact = 2, kPhNear = 3, kPhRows = 4, kPhases = 5 };
+
+// One image of a batch, as offsets from the bases passed at submission.
+struct BatchImage {
+    int64_t mask_off;  // bytes from the mask base
+    int64_t mpitch;    // bytes between mask rows
+    int64_t out_off;   // elements from the output bases
+    int64_t opitch;    // elements between output rows
+    int64_t ws_off;    // bytes from the workspace base
+    int32_t H, W, pol, want_feat;
+};
+
+// Device table of a batch: images, then for each phase the exclusive prefix
+// of work items over the images (nimg + 1 entries), and the bases.
+struct BatchTable {
+    const BatchImage* img;
+    const int32_t* prefix[kPhases];
+    int nimg;
+    const uint8_t* mask_base;
+    int32_t* dist_base;  // may be null
+    int32_t* feat_base;  // may be null
+    uint8_t* ws_base;
+};
+
+__device__ inline Img batch_img(const BatchTable& t, int im) {
+    const BatchImage b = t.img[im];
+    Img g;
+    g.mask = t.mask_base + b.mask_off;
+    g.mpitch = b.mpitch;
+    g.dist = t.dist_base ? t.dist_base + b.out_off : nullptr;
+    g.feat = (t.feat_base && b.want_feat) ? t.feat_base + b.out_off : nullptr;
+    g.opitch = b.opitch;
+    g.ws = t.ws_base + b.ws_off;
+    g.H = b.H;
+    g.W = b.W;
+    g.pol = b.pol;
+    return g;
+}
+
+// Image of work item `item` of phase p: the last image whose prefix is <= item.
+__device__ inline int batch_image_of(const BatchTable& t, int p, int item) {
+    const int32_t* pre = t.prefix[p];
+    int a = 0, b = t.nimg - 1;
+    while (a < b) {
+        const int mid = (a + b + 1) >> 1;
+        if (pre[mid] <= item)
+            a = mid;
+        else
+            b = mid - 1;
+    }
+    return a;
 }
 
 // Kernel timing (edt_profile_begin / edt_profile_end): a token from
@@ -94,13 +195,17 @@ void prof_end(int token, hipStream_t stream);
 #define EDT_LAUNCH(kernel, grid, block, lds, stream, ...) \
     EDT_LAUNCH_AS(#kernel, kernel, grid, block, lds, stream, __VA_ARGS__)
 
-// Launchers (enqueue on stream; return the HIP error of the launches).
-hipError_t launch_column_pass(const uint8_t* mask, int H, int W, int64_t pitch,
-                              int polarity, uint8_t* ws, const Layout& L,
-                              hipStream_t stream);
-hipError_t launch_row_pass(int H, int W, int32_t* dist, int32_t* feat,
-                           int64_t out_pitch, uint8_t* ws, const Layout& L,
-                           hipStream_t stream);
+// Number of compute units of the current device (cached per process).
+int device_cus();
+
+// Single image: the vertical pass and the row pass (enqueue on stream).
+hipError_t launch_column_pass(const Img& g, hipStream_t stream);
+hipError_t launch_row_pass(const Img& g, uint8_t* slots, hipStream_t stream);
+// A batch described by a device table (totals[p] = work items of phase p;
+// max_w = widest image, row forms are enqueued for the widths present).
+hipError_t launch_column_pass_batch(const BatchTable& t, const int* totals, hipStream_t stream);
+hipError_t launch_row_pass_batch(const BatchTable& t, const int* totals, int max_w,
+                                 hipStream_t stream);
 hipError_t launch_sqrt(const int32_t* D, float* out, int64_t n, hipStream_t stream);
 
 }  // namespace edt

@@ -41,6 +41,12 @@ Profiler& prof() {
 
 }  // namespace
 
+bool prof_enabled() {
+    Profiler& p = prof();
+    std::lock_guard<std::mutex> g(p.mu);
+    return p.on;
+}
+
 int prof_begin(const char* name, hipStream_t stream) {
     Profiler& p = prof();
     std::lock_guard<std::mutex> g(p.mu);

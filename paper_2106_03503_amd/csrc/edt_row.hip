@@ -196,36 +196,46 @@ __device__ __forceinline__ void store4(int32_t* __restrict__ p, int j, int W, bo
     }
 }
 
-// Row pass.  T lanes per row, S candidate slots per lane.  The sparse form
-// (one wavefront, kSparse) takes images with at most T*S candidate columns,
-// the dense form the others.  With kGlobal the candidate list lives in a
-// global-memory slot per workgroup instead of LDS.
+// Row pass over the rows [i0, i1) (step di) of one image.  T lanes per row, S
+// candidate slots per lane.  A form takes an image only if the image's
+// device-side count n of candidate columns is in its range: the sparse form
+// (one wavefront, kSparse) takes n <= T*S, each dense form the images with
+// n > kSparseMaxN whose width is in (T*S/2, T*S].  With kGlobal the candidate
+// list lives in the global-memory slot `gslot` instead of LDS.
 template <int T, int S, bool kSparse, bool kGlobal>
-__global__ __launch_bounds__(T) void k_row_envelope(
-    const int16_t* __restrict__ rc, const int16_t* __restrict__ cols,
-    const int32_t* __restrict__ meta, int H, int W, int32_t* __restrict__ dist,
-    int32_t* __restrict__ feat, int64_t out_pitch, int vec_out, uint8_t* __restrict__ slots) {
+struct RowLds {
+    static constexpr int CAP = kGlobal ? 1 : T * S;
+    uint32_t cand[CAP];
+    int16_t st[CAP];
+    int16_t lo[T], hi[T], nxt[T], prv[T], gf[T], gl[T];
+    int wsum[T / 64];
+};
+
+template <int T, int S, bool kSparse, bool kGlobal>
+__device__ __forceinline__ bool form_takes(int n, int W) {
+    if (kSparse) return n <= T * S;
+    return n > kSparseMaxN && W > T * S / 2 && W <= T * S;
+}
+
+template <int T, int S, bool kSparse, bool kGlobal>
+__device__ void process_rows(const Img& g, int i0, int i1, int di,
+                             RowLds<T, S, kSparse, kGlobal>& sh, uint8_t* gslot) {
     constexpr int NW = T / 64;
-    constexpr int CAP = kGlobal ? 1 : T * S;
     static_assert(!kGlobal || T * S <= kWideCap, "global row slot too small");
     static_assert((S & (S - 1)) == 0 && (T & (T - 1)) == 0, "T and S must be powers of two");
-    __shared__ uint32_t s_cand[CAP];
-    __shared__ int16_t s_st[CAP];
-    __shared__ int16_t s_lo[T], s_hi[T], s_nxt[T], s_prv[T], s_gf[T], s_gl[T];
-    __shared__ int s_wsum[NW];
-
-    const int n = meta[0];
-    if (kSparse ? (n > T * S) : (n <= kSparseMaxN)) return;  // the other form's image
-    const int pitch = meta[1];
+    const Views v = views_of(g);
+    const int n = v.meta[0];
+    const int W = g.W;
+    if (!form_takes<T, S, kSparse, kGlobal>(n, W)) return;  // another form's image
+    const int pitch = v.meta[1];
     uint32_t* cand;
     int16_t* st;
     if (kGlobal) {
-        uint8_t* slot = slots + (size_t)blockIdx.x * wide_slot_bytes(W);
-        cand = reinterpret_cast<uint32_t*>(slot);
-        st = reinterpret_cast<int16_t*>(slot + (size_t)kWideCap * 4);
+        cand = reinterpret_cast<uint32_t*>(gslot);
+        st = reinterpret_cast<int16_t*>(gslot + (size_t)kWideCap * 4);
     } else {
-        cand = s_cand;
-        st = s_st;
+        cand = sh.cand;
+        st = sh.st;
     }
     const Slots<T, S> sl{cand, st};
     const int t = threadIdx.x;
@@ -233,25 +243,27 @@ __global__ __launch_bounds__(T) void k_row_envelope(
     const int nchunks = (n + S - 1) / S;
     const int base = t * S;
     const int cnt = min(max(n - base, 0), S);
-    const bool vec = vec_out != 0;
+    const bool vec = (!g.dist || reinterpret_cast<uintptr_t>(g.dist) % 16 == 0) &&
+                     (!g.feat || reinterpret_cast<uintptr_t>(g.feat) % 16 == 0) &&
+                     (g.opitch % 4 == 0);
 
     // The candidate columns of this lane's chunk are the same in every row.
     uint32_t colhi[S];
 #pragma unroll
-    for (int u = 0; u < S; ++u) colhi[u] = u < cnt ? ((uint32_t)(uint16_t)cols[base + u] << 16) : 0u;
+    for (int u = 0; u < S; ++u) colhi[u] = u < cnt ? ((uint32_t)(uint16_t)v.cols[base + u] << 16) : 0u;
 
-    for (int i = blockIdx.x; i < H; i += gridDim.x) {
+    for (int i = i0; i < i1; i += di) {
         // 1. this row's candidates of the chunk: (column, nearest site row)
-        const int16_t* rrow = rc + (int64_t)i * pitch + base;
+        const int16_t* rrow = v.rc + (int64_t)i * pitch + base;
         if (cnt == S) {
             uint32_t w[S / 2];
 #pragma unroll
-            for (int v = 0; v < S / 8; ++v) {
-                const int4 x = reinterpret_cast<const int4*>(rrow)[v];
-                w[4 * v + 0] = (uint32_t)x.x;
-                w[4 * v + 1] = (uint32_t)x.y;
-                w[4 * v + 2] = (uint32_t)x.z;
-                w[4 * v + 3] = (uint32_t)x.w;
+            for (int q = 0; q < S / 8; ++q) {
+                const int4 x = reinterpret_cast<const int4*>(rrow)[q];
+                w[4 * q + 0] = (uint32_t)x.x;
+                w[4 * q + 1] = (uint32_t)x.y;
+                w[4 * q + 2] = (uint32_t)x.z;
+                w[4 * q + 3] = (uint32_t)x.w;
             }
 #pragma unroll
             for (int u = 0; u < S; ++u)
@@ -285,22 +297,22 @@ __global__ __launch_bounds__(T) void k_row_envelope(
                 ++m;
             }
         }
-        s_lo[t] = (int16_t)base;
-        s_hi[t] = (int16_t)(base + m);
-        s_nxt[t] = -1;
-        s_prv[t] = -1;
-        s_gf[t] = (int16_t)(m > 0 ? t : -1);
-        s_gl[t] = (int16_t)(m > 0 ? t : -1);
+        sh.lo[t] = (int16_t)base;
+        sh.hi[t] = (int16_t)(base + m);
+        sh.nxt[t] = -1;
+        sh.prv[t] = -1;
+        sh.gf[t] = (int16_t)(m > 0 ? t : -1);
+        sh.gl[t] = (int16_t)(m > 0 ? t : -1);
         __syncthreads();
         // 3. merge up the tree
         for (int w = 1; w < nchunks; w <<= 1) {
             if ((t & (2 * w - 1)) == 0 && t + w < nchunks)
-                merge_groups<T, S>(t, t + w, sl, s_lo, s_hi, s_nxt, s_prv, s_gf, s_gl, i, W);
+                merge_groups<T, S>(t, t + w, sl, sh.lo, sh.hi, sh.nxt, sh.prv, sh.gf, sh.gl, i, W);
             __syncthreads();
         }
         // 4. survivors to the front of the list, in column order (plain layout)
-        const int lo = s_lo[t];
-        const int c = s_hi[t] - lo;
+        const int lo = sh.lo[t];
+        const int c = sh.hi[t] - lo;
         uint32_t kc[S];
         int16_t ks[S];
 #pragma unroll
@@ -313,16 +325,16 @@ __global__ __launch_bounds__(T) void k_row_envelope(
         int incl = c;
 #pragma unroll
         for (int d = 1; d < 64; d <<= 1) {
-            const int v = __shfl_up(incl, d, 64);
-            if (lane >= d) incl += v;
+            const int x = __shfl_up(incl, d, 64);
+            if (lane >= d) incl += x;
         }
-        if (lane == 63) s_wsum[wave] = incl;
+        if (lane == 63) sh.wsum[wave] = incl;
         __syncthreads();
         int pos = incl - c, M = 0;
 #pragma unroll
         for (int q = 0; q < NW; ++q) {
-            if (q < wave) pos += s_wsum[q];
-            M += s_wsum[q];
+            if (q < wave) pos += sh.wsum[q];
+            M += sh.wsum[q];
         }
 #pragma unroll
         for (int u = 0; u < S; ++u) {
@@ -333,16 +345,16 @@ __global__ __launch_bounds__(T) void k_row_envelope(
         }
         __syncthreads();
         // 5. fill, four adjacent pixels per lane and step
-        int32_t* drow = dist ? dist + (int64_t)i * out_pitch : nullptr;
-        int32_t* frow = feat ? feat + (int64_t)i * out_pitch : nullptr;
+        int32_t* drow = g.dist ? g.dist + (int64_t)i * g.opitch : nullptr;
+        int32_t* frow = g.feat ? g.feat + (int64_t)i * g.opitch : nullptr;
         int e = 0;
         for (int j = 4 * t; j < W; j += 4 * T) {
             int d[4], f[4];
             if (M == 0) {
 #pragma unroll
-                for (int v = 0; v < 4; ++v) {
-                    d[v] = INT32_MAX;
-                    f[v] = -1;
+                for (int q = 0; q < 4; ++q) {
+                    d[q] = INT32_MAX;
+                    f[q] = -1;
                 }
             } else {
                 // owner of pixel j: the last survivor starting at or before j,
@@ -351,19 +363,19 @@ __global__ __launch_bounds__(T) void k_row_envelope(
                 uint32_t C = cand[e];
                 int nst = e + 1 < M ? st[e + 1] : INT32_MAX;
 #pragma unroll
-                for (int v = 0; v < 4; ++v) {
-                    const int jj = j + v;
+                for (int q = 0; q < 4; ++q) {
+                    const int jj = j + q;
                     if (jj < W) {
                         while (jj >= nst) {
                             ++e;
                             C = cand[e];
                             nst = e + 1 < M ? st[e + 1] : INT32_MAX;
                         }
-                        d[v] = parab(C, i, jj);
-                        f[v] = crow(C) * W + ccol(C);
+                        d[q] = parab(C, i, jj);
+                        f[q] = crow(C) * W + ccol(C);
                     } else {
-                        d[v] = 0;
-                        f[v] = 0;
+                        d[q] = 0;
+                        f[q] = 0;
                     }
                 }
             }
@@ -374,66 +386,95 @@ __global__ __launch_bounds__(T) void k_row_envelope(
     }
 }
 
+// One image: rows blockIdx.x, blockIdx.x + gridDim.x, ...
 template <int T, int S, bool kSparse, bool kGlobal>
-hipError_t launch_form(int H, int W, const int16_t* rc, const int16_t* cols,
-                       const int32_t* meta, int32_t* dist, int32_t* feat, int64_t out_pitch,
-                       int vec, uint8_t* slots, hipStream_t stream) {
+__global__ __launch_bounds__(T) void k_row_single(Img g, uint8_t* __restrict__ slots) {
+    __shared__ RowLds<T, S, kSparse, kGlobal> sh;
+    uint8_t* gslot = kGlobal ? slots + (size_t)blockIdx.x * wide_slot_bytes() : nullptr;
+    process_rows<T, S, kSparse, kGlobal>(g, blockIdx.x, g.H, gridDim.x, sh, gslot);
+}
+
+// A batch: workgroup g takes the contiguous run of row items
+// [g*chunk, (g+1)*chunk) across the images of the table, so that it stays on
+// one image for many rows.
+template <int T, int S, bool kSparse>
+__global__ __launch_bounds__(T) void k_row_batch(BatchTable tb, int total) {
+    __shared__ RowLds<T, S, kSparse, false> sh;
+    __shared__ int s_img;
+    const int chunk = (total + gridDim.x - 1) / gridDim.x;
+    int item = blockIdx.x * chunk;
+    const int end = min(total, item + chunk);
+    while (item < end) {
+        __syncthreads();
+        if (threadIdx.x == 0) s_img = batch_image_of(tb, kPhRows, item);
+        __syncthreads();
+        const int im = s_img;
+        const Img g = batch_img(tb, im);
+        const int r0 = item - tb.prefix[kPhRows][im];
+        const int r1 = min(g.H, end - tb.prefix[kPhRows][im]);
+        process_rows<T, S, kSparse, false>(g, r0, r1, 1, sh, nullptr);
+        item += r1 - r0;
+    }
+}
+
+template <typename K>
+int blocks_per_cu(K kernel, int threads) {
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kernel, threads, 0) != hipSuccess ||
+        nb < 1)
+        nb = 1;
+    return nb;
+}
+
+template <int T, int S, bool kSparse, bool kGlobal>
+hipError_t launch_single(const Img& g, uint8_t* slots, hipStream_t stream) {
     static int per_cu = 0;
-    if (per_cu == 0) {
-        int nb = 0;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
-                &nb, k_row_envelope<T, S, kSparse, kGlobal>, T, 0) != hipSuccess || nb < 1)
-            nb = 1;
-        per_cu = nb;
-    }
-    int cus = 256;
-    int dev = 0;
-    if (hipGetDevice(&dev) == hipSuccess) {
-        int v = 0;
-        if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess &&
-            v > 0)
-            cus = v;
-    }
-    int grid = per_cu * cus;
+    if (per_cu == 0) per_cu = blocks_per_cu(k_row_single<T, S, kSparse, kGlobal>, T);
+    int grid = per_cu * device_cus();
     if (kGlobal && grid > kWideSlots) grid = kWideSlots;
-    if (grid > H) grid = H;
+    if (grid > g.H) grid = g.H;
     const char* name = kSparse ? "k_row_sparse" : (kGlobal ? "k_row_dense_global" : "k_row_dense");
-    EDT_LAUNCH_AS(name, (k_row_envelope<T, S, kSparse, kGlobal>), dim3(grid), dim3(T), 0, stream,
-                  rc, cols, meta, H, W, dist, feat, out_pitch, vec, slots);
+    EDT_LAUNCH_AS(name, (k_row_single<T, S, kSparse, kGlobal>), dim3(grid), dim3(T), 0, stream,
+                  g, slots);
+    return hipGetLastError();
+}
+
+template <int T, int S, bool kSparse>
+hipError_t launch_batch(const BatchTable& tb, int total, hipStream_t stream) {
+    static int per_cu = 0;
+    if (per_cu == 0) per_cu = blocks_per_cu(k_row_batch<T, S, kSparse>, T);
+    int grid = per_cu * device_cus();
+    if (grid > total) grid = total;
+    if (grid < 1) return hipSuccess;
+    const char* name = kSparse ? "k_row_sparse" : "k_row_dense";
+    EDT_LAUNCH_AS(name, (k_row_batch<T, S, kSparse>), dim3(grid), dim3(T), 0, stream, tb, total);
     return hipGetLastError();
 }
 
 }  // namespace
 
-hipError_t launch_row_pass(int H, int W, int32_t* dist, int32_t* feat, int64_t out_pitch,
-                           uint8_t* ws, const Layout& L, hipStream_t stream) {
-    const int16_t* rc = reinterpret_cast<const int16_t*>(ws + L.rc);
-    const int16_t* cols = reinterpret_cast<const int16_t*>(ws + L.cols);
-    const int32_t* meta = reinterpret_cast<const int32_t*>(ws + L.meta);
-    uint8_t* slots = ws + L.slots;
-    const bool a16 = (!dist || reinterpret_cast<uintptr_t>(dist) % 16 == 0) &&
-                     (!feat || reinterpret_cast<uintptr_t>(feat) % 16 == 0);
-    const int vec = a16 && (out_pitch % 4 == 0);
+hipError_t launch_row_pass(const Img& g, uint8_t* slots, hipStream_t stream) {
     // Both forms are enqueued; each returns at once unless the image's number
     // of candidate columns (known only on the device) is in its range.
-    hipError_t e = launch_form<kSparseLanes, kRowS, true, false>(H, W, rc, cols, meta, dist,
-                                                                 feat, out_pitch, vec, slots,
-                                                                 stream);
+    hipError_t e = launch_single<kSparseLanes, kRowS, true, false>(g, slots, stream);
+    const int W = g.W;
     if (e != hipSuccess || W <= kSparseMaxN) return e;
-    if (W <= 2048)
-        return launch_form<128, kRowS, false, false>(H, W, rc, cols, meta, dist, feat,
-                                                     out_pitch, vec, slots, stream);
-    if (W <= 4096)
-        return launch_form<256, kRowS, false, false>(H, W, rc, cols, meta, dist, feat,
-                                                     out_pitch, vec, slots, stream);
-    if (W <= 8192)
-        return launch_form<512, kRowS, false, false>(H, W, rc, cols, meta, dist, feat,
-                                                     out_pitch, vec, slots, stream);
-    if (W <= kLdsMaxW)
-        return launch_form<1024, kRowS, false, false>(H, W, rc, cols, meta, dist, feat,
-                                                      out_pitch, vec, slots, stream);
-    return launch_form<1024, 2 * kRowS, false, true>(H, W, rc, cols, meta, dist, feat,
-                                                     out_pitch, vec, slots, stream);
+    if (W <= 2048) return launch_single<128, kRowS, false, false>(g, slots, stream);
+    if (W <= 4096) return launch_single<256, kRowS, false, false>(g, slots, stream);
+    if (W <= 8192) return launch_single<512, kRowS, false, false>(g, slots, stream);
+    if (W <= kLdsMaxW) return launch_single<1024, kRowS, false, false>(g, slots, stream);
+    return launch_single<1024, 2 * kRowS, false, true>(g, slots, stream);
+}
+
+hipError_t launch_row_pass_batch(const BatchTable& tb, const int* totals, int max_w,
+                                 hipStream_t stream) {
+    const int total = totals[kPhRows];
+    hipError_t e = launch_batch<kSparseLanes, kRowS, true>(tb, total, stream);
+    if (e == hipSuccess && max_w > 1024) e = launch_batch<128, kRowS, false>(tb, total, stream);
+    if (e == hipSuccess && max_w > 2048) e = launch_batch<256, kRowS, false>(tb, total, stream);
+    if (e == hipSuccess && max_w > 4096) e = launch_batch<512, kRowS, false>(tb, total, stream);
+    if (e == hipSuccess && max_w > 8192) e = launch_batch<1024, kRowS, false>(tb, total, stream);
+    return e;
 }
 
 }  // namespace edt

@@ -90,3 +90,27 @@ def test_python_binding_rejects_cpu_tensors(edt):
         edt.sq(torch.zeros((4, 4), dtype=torch.uint8))
     with pytest.raises(ValueError):
         edt.feature(torch.zeros((4, 4, 4), dtype=torch.uint8))
+
+
+def test_batch_plan_validation_before_any_device_call(edt):
+    import ctypes
+    from paper_2106_03503_amd import _lib
+    D = _lib.ImageDesc
+
+    def plan(descs, n=None, want_dist=1):
+        arr = (D * max(1, len(descs)))(*descs)
+        p = ctypes.c_void_p()
+        ws = ctypes.c_size_t()
+        return _lib.lib.edt_batch_plan(ctypes.cast(arr, ctypes.c_void_p),
+                                       len(descs) if n is None else n, want_dist,
+                                       ctypes.byref(p), ctypes.byref(ws))
+
+    ok = D(0, 16, 0, 16, 8, 16, 0, 1)
+    assert plan([ok], n=0) == -1
+    assert plan([D(0, 16, 0, 16, 0, 16, 0, 1)]) == -3          # H = 0
+    assert plan([D(0, 20000, 0, 20000, 4, 20000, 0, 1)]) == -3  # wider than a batch allows
+    assert plan([D(0, 8, 0, 16, 8, 16, 0, 1)]) == -1           # mask pitch < W
+    assert plan([D(0, 16, 0, 8, 8, 16, 0, 1)]) == -1           # out pitch < W
+    assert plan([D(0, 16, 0, 16, 8, 16, 5, 1)]) == -1          # polarity
+    assert plan([D(-16, 16, 0, 16, 8, 16, 0, 1)]) == -1        # negative offset
+    assert _lib.lib.edt_plan_destroy(None) == -1
