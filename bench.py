@@ -13,6 +13,12 @@ Workloads (--workload):
                        polarity), replayed as a captured graph; the same
                        images launched one by one through edt_feature are
                        timed beside it ("per_image").
+  serve                one step = one replay of a Poisson request stream
+                       (--rate requests/s, --requests of them; square masks
+                       of side 128..8192 log-uniform, Bernoulli or ellipses,
+                       half distance-only) through the request server; reports
+                       throughput and p50/p99 latency (submission to observed
+                       completion).
 Inputs are resident in HBM before the timed region.  Prints ONE JSON line.
 --gpus N > 1 is refused: this build runs on one GPU.
 """
@@ -79,6 +85,10 @@ SINGLE = {
 BATCH_DESC = ("2048 uint8 masks of uneven size (H, W uniform in 64..1024), 5-60 overlapping "
               "random ellipses each (semi-axes 4-80), polarity Bernoulli(0.5); int32 squared "
               "distance + int32 nearest-site index per pixel")
+SERVE_DESC = ("{n} requests arriving as a Poisson stream at {rate:g}/s: square uint8 masks of "
+              "side round(exp(U(ln 128, ln 8192))), Bernoulli or ellipses (50/50) at "
+              "log-uniform density 1e-4..0.3; half int32 squared distance only, half distance + "
+              "nearest-site index")
 
 
 def make_mask(name):
@@ -279,25 +289,119 @@ def run_batch(args):
     return out
 
 
+def run_serve(args):
+    import numpy as np
+    import torch
+    import paper_2106_03503_amd as edt
+    import workloads
+    reqs = workloads.serving_requests(args.requests, args.rate)
+    dev = torch.device("cuda:0")
+    print(f"serve: drawing {len(reqs)} request masks", file=sys.stderr, flush=True)
+    masks_np = [workloads.request_mask(r) for r in reqs]
+    masks = [torch.from_numpy(m).to(dev) for m in masks_np]
+    outs = []
+    for r in reqs:
+        s_ = r["side"]
+        D = torch.empty((s_, s_), dtype=torch.int32, device=dev)
+        F = torch.empty((s_, s_), dtype=torch.int32, device=dev) if r["want_feature"] else None
+        outs.append((D, F))
+    torch.cuda.synchronize()
+    px = sum(m.numel() for m in masks)
+    bytes_path = sum((13 if r["want_feature"] else 9) * r["side"] ** 2 for r in reqs)
+    budget = int(args.budget_gib * (1 << 30))
+    stream = torch.cuda.current_stream()
+
+    def replay(srv):
+        t0 = time.perf_counter()
+        tickets = []
+        for r, m, (D, F) in zip(reqs, masks, outs):
+            while time.perf_counter() - t0 < r["t"]:
+                pass
+            while True:
+                try:
+                    tickets.append(srv.submit_raw(m, D, F, polarity=r["polarity"], stream=stream))
+                    break
+                except edt.EDTError as e:
+                    if e.status != -5:  # busy: retry
+                        raise
+                    time.sleep(50e-6)
+        for t in tickets:
+            srv.wait(t)
+        return time.perf_counter() - t0, srv.stats()
+
+    if args.warmup > 0:  # one warm-up replay
+        with edt.Server(budget, n_streams=args.streams) as srv:
+            replay(srv)
+    runs = []
+    for k in range(args.steps):
+        with edt.Server(budget, n_streams=args.streams) as srv:
+            wall, st = replay(srv)
+        runs.append((wall, st))
+        print(f"serve: replay {k + 1}/{args.steps} {wall * 1e3:.1f} ms", file=sys.stderr, flush=True)
+    walls = [w for w, _ in runs]
+    med = sorted(range(len(runs)), key=lambda q: walls[q])[len(runs) // 2]
+    wall, st = runs[med]
+    value = st["gpix_per_s"]
+    out = base_line(args, value, wall * 1e3,
+                    {"workload": SERVE_DESC.format(n=len(reqs), rate=args.rate),
+                     "requests": len(reqs), "pixels": int(px), "rate_per_s": args.rate,
+                     "hbm_budget_GiB": args.budget_gib, "streams": args.streams,
+                     "call": "edt_serve_submit / edt_serve_wait", "parallelism": "single GPU"})
+    out["scaling"] = "strong"
+    offered = px / reqs[-1]["t"] / 1e9
+    gbs = bytes_path / (px / (value * 1e9)) / 1e9 if value > 0 else 0.0
+    out["serve"] = {"offered_gpix_per_s": round(offered, 3),
+                    "p50_ms": round(st["p50_ns"] / 1e6, 3), "p99_ms": round(st["p99_ns"] / 1e6, 3),
+                    "mean_ms": round(st["mean_ns"] / 1e6, 3), "max_ms": round(st["max_ns"] / 1e6, 3),
+                    "launches": st["launches"], "done": st["done"], "failed": st["failed"],
+                    "rejected_busy": st["rejected_busy"],
+                    "hbm_high_water_GiB": round(st["hbm_high_water"] / (1 << 30), 3),
+                    "replay_ms": [round(w * 1e3, 2) for w in walls]}
+    out["path_hbm"] = {"bytes_per_px": round(bytes_path / px, 3), "achieved_GBs": round(gbs, 1),
+                       "frac": round(gbs / HBM_PEAK_GBS, 4)}
+    if not args.no_cpu:
+        # a bounded sample: the requests in arrival order up to ~1e8 pixels
+        sample, acc = [], 0
+        for m, r in zip(masks_np, reqs):
+            if acc + m.size > 1e8 and sample:
+                break
+            sample.append((m, r["polarity"]))
+            acc += m.size
+        cb = cpu_baseline(sample, acc)
+        cb["sample"] = (f"the first {len(sample)} requests of the stream ({acc} pixels), "
+                        f"one after the other: " + cb["sample"])
+        out["cpu_baseline"] = cb
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="points16k",
-                    choices=sorted(list(SINGLE) + ["batch2048"]))
+                    choices=sorted(list(SINGLE) + ["batch2048", "serve"]))
+    ap.add_argument("--rate", type=float, default=5000.0, help="serve: requests per second")
+    ap.add_argument("--requests", type=int, default=400, help="serve: requests per replay")
+    ap.add_argument("--budget-gib", type=float, default=16.0, help="serve: memory budget")
+    ap.add_argument("--streams", type=int, default=4, help="serve: server streams")
     ap.add_argument("--no-cpu", action="store_true", help="skip the cpu_baseline leg")
     ap.add_argument("--copy-calibration", action="store_true")
     args = ap.parse_args()
 
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
-              "(see DESIGN.md, 'More than one GPU').", file=sys.stderr)
+        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported.",
+              file=sys.stderr)
         sys.exit(2)
     if args.copy_calibration:
         copy_calibration(args.steps)
         return
-    out = run_batch(args) if args.workload == "batch2048" else run_single(args)
+    if args.workload == "batch2048":
+        out = run_batch(args)
+    elif args.workload == "serve":
+        out = run_serve(args)
+    else:
+        out = run_single(args)
     print(json.dumps(out), flush=True)
 
 

@@ -160,6 +160,100 @@ edt_status edt_batch_submit(edt_plan *plan, const uint8_t *mask_base, int32_t *d
  * it must have completed. */
 edt_status edt_plan_destroy(edt_plan *plan);
 
+/* ---- serving: continuous batching of independent requests -------------- */
+
+/* A server owns a scheduler thread and n_streams HIP streams of the current
+ * device.  Requests (one image each, with caller-owned device mask and
+ * outputs) queue in arrival order; whenever launch slots are free, the
+ * scheduler admits the longest prefix of the queue whose workspaces fit in
+ * the memory budget and launches it at once, as one batch (the persistent
+ * launches of edt_batch_submit) or, for a lone request or a row wider than
+ * EDT_BATCH_MAX_W, as a single transform.  Requests arriving meanwhile join
+ * the next launch.  Workspaces are carved from a caller-owned device arena.
+ * Results are bit-identical to edt_feature / edt_sq on the request alone. */
+typedef struct {
+    size_t hbm_budget_bytes; /* arena bytes the server may hold at once for
+                                admitted work (<= arena_bytes; 0: the whole arena) */
+    int32_t max_inflight;    /* requests queued or running at once, >= 1;
+                                one more is refused with EDT_ERR_BUSY */
+    int32_t n_streams;       /* streams launched on, 1..EDT_SERVE_MAX_STREAMS */
+    int32_t max_group;       /* most requests per launch, 1..EDT_SERVE_MAX_GROUP
+                                (0: EDT_SERVE_MAX_GROUP) */
+} edt_serve_config;
+
+#define EDT_SERVE_MAX_STREAMS 16
+#define EDT_SERVE_MAX_GROUP 1024
+
+/* One request. */
+typedef struct {
+    const uint8_t *mask; /* device, H x W, rows mask_pitch bytes apart */
+    int64_t mask_pitch;
+    int32_t H, W;        /* 1 <= H, W <= EDT_MAX_SIDE */
+    int32_t polarity;    /* EDT_TO_OBJECT or EDT_TO_BACKGROUND */
+    int32_t reserved;    /* must be 0 */
+    int32_t *dist_sq;    /* device or NULL: squared distances, out_pitch elements */
+    int32_t *feature;    /* device or NULL (not both NULL): nearest-site indices */
+    int64_t out_pitch;
+    void *stream;        /* the mask is read only after the work enqueued on
+                            this stream (NULL: the default stream) before the
+                            submission; outputs are complete when the ticket
+                            is done */
+} edt_request;
+
+typedef struct {
+    uint64_t submitted;          /* accepted by edt_serve_submit */
+    uint64_t rejected_busy;      /* refused with EDT_ERR_BUSY */
+    uint64_t rejected_too_large; /* refused with EDT_ERR_TOO_LARGE */
+    uint64_t done;               /* completed, successfully or not */
+    uint64_t failed;             /* completed with an error */
+    uint64_t launches;           /* groups launched */
+    uint64_t pixels_done;        /* sum of H*W over the successful requests */
+    double p50_ns, p99_ns, mean_ns, max_ns; /* latency, submission to observed
+                                               completion, over done requests */
+    double gpix_per_s;           /* pixels_done / (last completion - first submission) */
+    size_t hbm_in_use;           /* arena bytes held by admitted requests now */
+    size_t hbm_high_water;       /* most such bytes ever held at once */
+} edt_serve_counters;
+
+typedef struct edt_server edt_server;
+
+/* Create a server on the current device.  cfg is host memory; arena is a
+ * device buffer of arena_bytes (256-byte aligned) that the server uses as
+ * workspace until edt_serve_destroy returns.  Errors: EDT_ERR_INVALID_ARG,
+ * EDT_ERR_OUT_OF_MEMORY, EDT_ERR_DEVICE. */
+edt_status edt_serve_create(const edt_serve_config *cfg, void *arena, size_t arena_bytes,
+                            edt_server **out);
+
+/* Bytes at the start of the arena that a server with this configuration keeps
+ * for its launch tables (2 * n_streams tables of max_group images); they come
+ * out of the memory budget.  0 for an invalid configuration. */
+size_t edt_serve_reserved_bytes(const edt_serve_config *cfg);
+
+/* Queue one request (host struct; its device buffers must stay valid until
+ * the ticket is done).  *ticket (host) receives its ticket.  Errors:
+ * EDT_ERR_INVALID_ARG or EDT_ERR_TOO_LARGE (also when the request alone needs
+ * more than the memory budget), EDT_ERR_BUSY (max_inflight requests are
+ * queued or running; retry later). */
+edt_status edt_serve_submit(edt_server *s, const edt_request *r, uint64_t *ticket);
+
+/* *done (host) = 1 once the ticket has completed, else 0.  Returns the
+ * request's own status once done (EDT_OK, or EDT_ERR_DEVICE if its launch
+ * failed), EDT_OK while it is pending, EDT_ERR_INVALID_ARG for an unknown
+ * ticket. */
+edt_status edt_serve_poll(edt_server *s, uint64_t ticket, int32_t *done);
+
+/* Block until the ticket completes (timeout_ns < 0: no limit) and return its
+ * status; EDT_ERR_NOT_READY if the time ran out first. */
+edt_status edt_serve_wait(edt_server *s, uint64_t ticket, int64_t timeout_ns);
+
+/* Counters and latency percentiles so far (host struct). */
+edt_status edt_serve_stats(edt_server *s, edt_serve_counters *out);
+
+/* Finish all queued and running requests, then release the server's
+ * threads, streams and host memory (not the arena).  Returns EDT_ERR_DEVICE
+ * if any request failed. */
+edt_status edt_serve_destroy(edt_server *s);
+
 /* ---- kernel timing (observability) ------------------------------------ */
 
 /* Total device time of one kernel of the library between edt_profile_begin

@@ -9,6 +9,7 @@ transform runs in the library's HIP kernels; there is no fallback.
     D = edt.sq(mask)                 # int32 squared distances
     D, F = edt.feature(mask)         # + nearest-site linear index
     d = edt.sqrt_f32(D)              # float32 distances
+    srv = edt.Server(1 << 30)        # request server: submit / wait / stats
 """
 from ._lib import (  # noqa: F401
     EDT_INF_SQ,
@@ -16,6 +17,7 @@ from ._lib import (  # noqa: F401
     EDT_TO_BACKGROUND,
     EDT_TO_OBJECT,
     BatchPlan,
+    Server,
     EDTError,
     abi_version,
     feature,

@@ -286,3 +286,155 @@ class BatchPlan:
             self.close()
         except Exception:
             pass
+
+
+# ---------------------------------------------------------------- serving
+
+EDT_ERR_BUSY = -5
+EDT_ERR_NOT_READY = -6
+
+
+class ServeConfig(ctypes.Structure):
+    _fields_ = [("hbm_budget_bytes", ctypes.c_size_t), ("max_inflight", ctypes.c_int32),
+                ("n_streams", ctypes.c_int32), ("max_group", ctypes.c_int32)]
+
+
+class Request(ctypes.Structure):
+    _fields_ = [("mask", ctypes.c_void_p), ("mask_pitch", ctypes.c_int64),
+                ("H", ctypes.c_int32), ("W", ctypes.c_int32),
+                ("polarity", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("dist_sq", ctypes.c_void_p), ("feature", ctypes.c_void_p),
+                ("out_pitch", ctypes.c_int64), ("stream", ctypes.c_void_p)]
+
+
+class ServeCounters(ctypes.Structure):
+    _fields_ = [("submitted", ctypes.c_uint64), ("rejected_busy", ctypes.c_uint64),
+                ("rejected_too_large", ctypes.c_uint64), ("done", ctypes.c_uint64),
+                ("failed", ctypes.c_uint64), ("launches", ctypes.c_uint64),
+                ("pixels_done", ctypes.c_uint64), ("p50_ns", ctypes.c_double),
+                ("p99_ns", ctypes.c_double), ("mean_ns", ctypes.c_double),
+                ("max_ns", ctypes.c_double), ("gpix_per_s", ctypes.c_double),
+                ("hbm_in_use", ctypes.c_size_t), ("hbm_high_water", ctypes.c_size_t)]
+
+
+def _bind_serve():
+    P, i32, i64, sz = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_size_t
+    _lib.edt_serve_create.argtypes = [P, P, sz, P]
+    _lib.edt_serve_create.restype = i32
+    _lib.edt_serve_submit.argtypes = [P, P, P]
+    _lib.edt_serve_submit.restype = i32
+    _lib.edt_serve_poll.argtypes = [P, ctypes.c_uint64, P]
+    _lib.edt_serve_poll.restype = i32
+    _lib.edt_serve_wait.argtypes = [P, ctypes.c_uint64, i64]
+    _lib.edt_serve_wait.restype = i32
+    _lib.edt_serve_stats.argtypes = [P, P]
+    _lib.edt_serve_stats.restype = i32
+    _lib.edt_serve_destroy.argtypes = [P]
+    _lib.edt_serve_destroy.restype = i32
+    _lib.edt_serve_reserved_bytes.argtypes = [P]
+    _lib.edt_serve_reserved_bytes.restype = sz
+
+
+_bind_serve()
+
+
+class Server:
+    """Request server over the library's scheduler (edt_serve_*).
+
+    The arena (``arena_bytes`` of device memory, allocated here with torch)
+    holds the workspaces of admitted requests; ``hbm_budget`` (default: the
+    arena) caps what admitted work may hold at once.  ``submit`` returns a
+    ticket; the tensors of a request are kept alive here until its ticket has
+    been waited for."""
+
+    def __init__(self, arena_bytes: int, hbm_budget: int = 0, max_inflight: int = 1024,
+                 n_streams: int = 4, max_group: int = 0, device=None):
+        device = torch.device("cuda", torch.cuda.current_device()) if device is None else device
+        self.device = device
+        self.arena = torch.empty(int(arena_bytes), dtype=torch.uint8, device=device)
+        cfg = ServeConfig(int(hbm_budget), int(max_inflight), int(n_streams), int(max_group))
+        self._srv = ctypes.c_void_p()
+        _check(_lib.edt_serve_create(ctypes.byref(cfg), self.arena.data_ptr(),
+                                     self.arena.numel(), ctypes.byref(self._srv)),
+               "edt_serve_create")
+        self._held = {}
+
+    @staticmethod
+    def reserved_bytes(n_streams: int = 4, max_group: int = 0) -> int:
+        """Arena bytes a server keeps for its launch tables."""
+        cfg = ServeConfig(0, 1, int(n_streams), int(max_group))
+        return int(_lib.edt_serve_reserved_bytes(ctypes.byref(cfg)))
+
+    def submit_raw(self, mask: torch.Tensor, dist, feat, polarity: int = EDT_TO_OBJECT,
+                   stream=None) -> int:
+        """Queue a request with caller-made outputs (int32 (H, W) tensors, one
+        of them may be None).  Returns the ticket; raises EDTError (status
+        EDT_ERR_BUSY when the server is full)."""
+        mask = _check_mask(mask)
+        H, W = mask.shape
+        pitch = None
+        for t in (dist, feat):
+            if t is not None:
+                _check_out(t, H, W, mask.device, "output")
+                if pitch is not None and t.stride(0) != pitch:
+                    raise ValueError("outputs must share one row pitch")
+                pitch = t.stride(0)
+        if pitch is None:
+            raise ValueError("at least one output is needed")
+        req = Request(mask.data_ptr(), mask.stride(0), H, W, int(polarity), 0,
+                      dist.data_ptr() if dist is not None else None,
+                      feat.data_ptr() if feat is not None else None, pitch,
+                      _stream_ptr(stream))
+        ticket = ctypes.c_uint64(0)
+        _check(_lib.edt_serve_submit(self._srv, ctypes.byref(req), ctypes.byref(ticket)),
+               "edt_serve_submit")
+        self._held[ticket.value] = (mask, dist, feat)
+        return ticket.value
+
+    def submit(self, mask: torch.Tensor, polarity: int = EDT_TO_OBJECT,
+               want_dist: bool = True, want_feature: bool = False, stream=None) -> int:
+        """Queue a request; outputs are allocated here and returned by wait()."""
+        H, W = mask.shape
+        dist = torch.empty((H, W), dtype=torch.int32, device=mask.device) if want_dist else None
+        feat = torch.empty((H, W), dtype=torch.int32, device=mask.device) if want_feature else None
+        return self.submit_raw(mask, dist, feat, polarity, stream)
+
+    def poll(self, ticket: int) -> bool:
+        done = ctypes.c_int32(0)
+        _check(_lib.edt_serve_poll(self._srv, ticket, ctypes.byref(done)), "edt_serve_poll")
+        return bool(done.value)
+
+    def wait(self, ticket: int, timeout: float | None = None):
+        """Wait for a ticket; returns its (dist, feature) tensors (None where
+        not requested).  Raises EDTError with EDT_ERR_NOT_READY on timeout."""
+        ns = -1 if timeout is None else int(timeout * 1e9)
+        st = _lib.edt_serve_wait(self._srv, ticket, ns)
+        if st == EDT_ERR_NOT_READY:
+            raise EDTError(st, "edt_serve_wait")
+        held = self._held.pop(ticket, (None, None, None))
+        _check(st, "edt_serve_wait")
+        return held[1], held[2]
+
+    def stats(self) -> dict:
+        c = ServeCounters()
+        _check(_lib.edt_serve_stats(self._srv, ctypes.byref(c)), "edt_serve_stats")
+        return {name: getattr(c, name) for name, _ in ServeCounters._fields_}
+
+    def close(self):
+        if self._srv:
+            st = _lib.edt_serve_destroy(self._srv)
+            self._srv = ctypes.c_void_p()
+            self._held.clear()
+            _check(st, "edt_serve_destroy")
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -23,7 +23,8 @@ ROCM = os.environ.get("ROCM_PATH", "/opt/rocm")
 HIPCC = os.path.join(ROCM, "bin", "hipcc")
 CLANGXX = os.path.join(ROCM, "llvm", "bin", "clang++")
 
-SOURCES = ["edt_api.hip", "edt_column.hip", "edt_row.hip", "edt_batch.hip", "edt_profile.hip"]
+SOURCES = ["edt_api.hip", "edt_column.hip", "edt_row.hip", "edt_batch.hip", "edt_profile.hip",
+           "edt_serve.hip"]
 
 HIP_FLAGS = [
     "--offload-arch=gfx950",

@@ -60,9 +60,13 @@ static edt_status run(const uint8_t* mask, int32_t H, int32_t W, int64_t mask_pi
     g.H = H;
     g.W = W;
     g.pol = polarity;
-    if (launch_column_pass(g, s) != hipSuccess) return EDT_ERR_DEVICE;
-    if (launch_row_pass(g, g.ws + L.slots, s) != hipSuccess) return EDT_ERR_DEVICE;
-    return EDT_OK;
+    return enqueue_single(g, s) == hipSuccess ? EDT_OK : EDT_ERR_DEVICE;
+}
+
+hipError_t enqueue_single(const Img& g, hipStream_t stream) {
+    hipError_t e = launch_column_pass(g, stream);
+    if (e == hipSuccess) e = launch_row_pass(g, g.ws + layout_for(g.H, g.W).slots, stream);
+    return e;
 }
 
 }  // namespace edt

@@ -7,14 +7,59 @@
 #include "edt_internal.h"
 
 #include <cstdlib>
+#include <cstring>
 #include <new>
 #include <vector>
 
 namespace edt {
 
-edt_status check_image(const uint8_t* mask, int32_t H, int32_t W, int64_t mask_pitch,
-                       int32_t polarity, int32_t metric, int64_t out_pitch);
-bool prof_enabled();
+size_t table_bytes(int n) {
+    return align_up(sizeof(BatchImage) * (size_t)n, 256) +
+           kPhases * align_up(sizeof(int32_t) * ((size_t)n + 1), 256);
+}
+
+int32_t pack_table(const BatchImage* img, int n, uint8_t* dst, int* totals, int* max_w) {
+    const size_t img_bytes = align_up(sizeof(BatchImage) * (size_t)n, 256);
+    const size_t pre_bytes = align_up(sizeof(int32_t) * ((size_t)n + 1), 256);
+    memcpy(dst, img, sizeof(BatchImage) * (size_t)n);
+    int64_t acc[kPhases] = {0, 0, 0, 0, 0};
+    int mw = 0;
+    for (int q = 0; q < n; ++q) {
+        const int H = img[q].H, W = img[q].W;
+        const int64_t items[kPhases] = {items_bits(H, W), items_carry(H, W), 1, items_near(H, W), H};
+        for (int p = 0; p < kPhases; ++p) {
+            int32_t* pre = reinterpret_cast<int32_t*>(dst + img_bytes + p * pre_bytes);
+            pre[q] = (int32_t)acc[p];
+            acc[p] += items[p];
+            if (acc[p] > INT32_MAX) return EDT_ERR_TOO_LARGE;
+        }
+        if (W > mw) mw = W;
+    }
+    for (int p = 0; p < kPhases; ++p) {
+        reinterpret_cast<int32_t*>(dst + img_bytes + p * pre_bytes)[n] = (int32_t)acc[p];
+        totals[p] = (int)acc[p];
+    }
+    *max_w = mw;
+    return EDT_OK;
+}
+
+BatchTable table_view(const uint8_t* dev_table, int n) {
+    const size_t img_bytes = align_up(sizeof(BatchImage) * (size_t)n, 256);
+    const size_t pre_bytes = align_up(sizeof(int32_t) * ((size_t)n + 1), 256);
+    BatchTable t;
+    t.img = reinterpret_cast<const BatchImage*>(dev_table);
+    for (int p = 0; p < kPhases; ++p)
+        t.prefix[p] = reinterpret_cast<const int32_t*>(dev_table + img_bytes + p * pre_bytes);
+    t.nimg = n;
+    t.mask_base = t.dist_base = t.feat_base = t.ws_base = 0;
+    return t;
+}
+
+hipError_t enqueue_batch(const BatchTable& t, const int* totals, int max_w, hipStream_t s) {
+    hipError_t e = launch_column_pass_batch(t, totals, s);
+    if (e == hipSuccess) e = launch_row_pass_batch(t, totals, max_w, s);
+    return e;
+}
 
 }  // namespace edt
 
@@ -26,9 +71,7 @@ struct edt_plan {
     int totals[edt::kPhases] = {0, 0, 0, 0, 0};
     size_t ws_bytes = 0;
     int device = 0;
-    void* table = nullptr;  // device: BatchImage[nimg], then prefix arrays
-    const edt::BatchImage* img_dev = nullptr;
-    const int32_t* prefix_dev[edt::kPhases] = {};
+    void* table = nullptr;  // device copy of the batch table
     // captured launches for one set of buffers
     hipStream_t cap_stream = nullptr;
     hipGraph_t graph = nullptr;
@@ -49,9 +92,7 @@ void drop_graph(edt_plan* p) {
 }
 
 hipError_t enqueue(edt_plan* p, const edt::BatchTable& t, hipStream_t s) {
-    hipError_t e = edt::launch_column_pass_batch(t, p->totals, s);
-    if (e == hipSuccess) e = edt::launch_row_pass_batch(t, p->totals, p->max_w, s);
-    return e;
+    return edt::enqueue_batch(t, p->totals, p->max_w, s);
 }
 
 }  // namespace
@@ -64,11 +105,8 @@ edt_status edt_batch_plan(const edt_image_desc* images, int32_t n, int32_t want_
     if (n > EDT_BATCH_MAX_IMAGES) return EDT_ERR_TOO_LARGE;
     *plan = nullptr;
     std::vector<edt::BatchImage> img(n);
-    std::vector<int32_t> prefix[edt::kPhases];
-    for (auto& v : prefix) v.assign((size_t)n + 1, 0);
-    int64_t acc[edt::kPhases] = {0, 0, 0, 0, 0};
     size_t ws = 0;
-    int max_w = 0, any_feat = 0;
+    int any_feat = 0;
     for (int q = 0; q < n; ++q) {
         const edt_image_desc& d = images[q];
         // the pointers are only checked for null later; a dummy non-null mask
@@ -82,25 +120,21 @@ edt_status edt_batch_plan(const edt_image_desc* images, int32_t n, int32_t want_
         edt::BatchImage& b = img[q];
         b.mask_off = d.mask_offset;
         b.mpitch = d.mask_pitch;
-        b.out_off = d.out_offset;
+        b.dist_off = d.out_offset;
+        b.feat_off = d.out_offset;
         b.opitch = d.out_pitch;
         b.ws_off = (int64_t)ws;
         b.H = d.H;
         b.W = d.W;
         b.pol = d.polarity;
-        b.want_feat = d.want_feature != 0;
-        any_feat |= b.want_feat;
-        if (d.W > max_w) max_w = d.W;
+        b.outs = (want_dist ? edt::kOutDist : 0) | (d.want_feature ? edt::kOutFeat : 0);
+        any_feat |= d.want_feature != 0;
         ws += edt::layout_for(d.H, d.W, false).total;
-        const int64_t items[edt::kPhases] = {edt::items_bits(d.H, d.W), edt::items_carry(d.H, d.W), 1,
-                                             edt::items_near(d.H, d.W), d.H};
-        for (int p = 0; p < edt::kPhases; ++p) {
-            prefix[p][q] = (int32_t)acc[p];
-            acc[p] += items[p];
-            if (acc[p] > INT32_MAX) return EDT_ERR_TOO_LARGE;
-        }
     }
-    for (int p = 0; p < edt::kPhases; ++p) prefix[p][n] = (int32_t)acc[p];
+    std::vector<uint8_t> host(edt::table_bytes(n));
+    int totals[edt::kPhases], max_w = 0;
+    const edt_status pst = edt::pack_table(img.data(), n, host.data(), totals, &max_w);
+    if (pst != EDT_OK) return pst;
 
     edt_plan* pl = new (std::nothrow) edt_plan;
     if (!pl) return EDT_ERR_OUT_OF_MEMORY;
@@ -108,26 +142,14 @@ edt_status edt_batch_plan(const edt_image_desc* images, int32_t n, int32_t want_
     pl->want_dist = want_dist != 0;
     pl->any_feat = any_feat;
     pl->max_w = max_w;
-    for (int p = 0; p < edt::kPhases; ++p) pl->totals[p] = (int)acc[p];
+    for (int p = 0; p < edt::kPhases; ++p) pl->totals[p] = totals[p];
     pl->ws_bytes = ws;
     pl->use_graph = std::getenv("EDT_NO_GRAPH") == nullptr;
-    const size_t img_bytes = edt::align_up(sizeof(edt::BatchImage) * (size_t)n, 256);
-    const size_t pre_bytes = edt::align_up(sizeof(int32_t) * ((size_t)n + 1), 256);
-    const size_t table_bytes = img_bytes + edt::kPhases * pre_bytes;
-    if (hipGetDevice(&pl->device) != hipSuccess || hipMalloc(&pl->table, table_bytes) != hipSuccess) {
+    if (hipGetDevice(&pl->device) != hipSuccess || hipMalloc(&pl->table, host.size()) != hipSuccess) {
         delete pl;
         return EDT_ERR_OUT_OF_MEMORY;
     }
-    uint8_t* tb = static_cast<uint8_t*>(pl->table);
-    bool ok = hipMemcpy(tb, img.data(), sizeof(edt::BatchImage) * (size_t)n,
-                        hipMemcpyHostToDevice) == hipSuccess;
-    pl->img_dev = reinterpret_cast<const edt::BatchImage*>(tb);
-    for (int p = 0; p < edt::kPhases && ok; ++p) {
-        uint8_t* dst = tb + img_bytes + p * pre_bytes;
-        ok = hipMemcpy(dst, prefix[p].data(), sizeof(int32_t) * ((size_t)n + 1),
-                       hipMemcpyHostToDevice) == hipSuccess;
-        pl->prefix_dev[p] = reinterpret_cast<const int32_t*>(dst);
-    }
+    bool ok = hipMemcpy(pl->table, host.data(), host.size(), hipMemcpyHostToDevice) == hipSuccess;
     if (ok) ok = hipEventCreateWithFlags(&pl->done, hipEventDisableTiming) == hipSuccess;
     if (ok && pl->use_graph)
         ok = hipStreamCreateWithFlags(&pl->cap_stream, hipStreamNonBlocking) == hipSuccess;
@@ -150,20 +172,18 @@ edt_status edt_batch_submit(edt_plan* p, const uint8_t* mask_base, int32_t* dist
     if (workspace_bytes < p->ws_bytes || (reinterpret_cast<uintptr_t>(workspace) & 255) != 0)
         return EDT_ERR_INVALID_ARG;
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-    edt::BatchTable t;
-    t.img = p->img_dev;
-    for (int q = 0; q < edt::kPhases; ++q) t.prefix[q] = p->prefix_dev[q];
-    t.nimg = p->nimg;
-    t.mask_base = mask_base;
-    t.dist_base = p->want_dist ? dist_base : nullptr;
-    t.feat_base = p->any_feat ? feat_base : nullptr;
-    t.ws_base = static_cast<uint8_t*>(workspace);
+    edt::BatchTable t = edt::table_view(static_cast<const uint8_t*>(p->table), p->nimg);
+    t.mask_base = reinterpret_cast<uintptr_t>(mask_base);
+    t.dist_base = p->want_dist ? reinterpret_cast<uintptr_t>(dist_base) : 0;
+    t.feat_base = p->any_feat ? reinterpret_cast<uintptr_t>(feat_base) : 0;
+    t.ws_base = reinterpret_cast<uintptr_t>(workspace);
     // Kernel timing needs the launches themselves, so it bypasses the graph.
     if (!p->use_graph || edt::prof_enabled()) {
         if (enqueue(p, t, s) != hipSuccess) return EDT_ERR_DEVICE;
         return hipEventRecord(p->done, s) == hipSuccess ? EDT_OK : EDT_ERR_DEVICE;
     }
-    const void* key[4] = {mask_base, t.dist_base, t.feat_base, workspace};
+    const void* key[4] = {mask_base, p->want_dist ? dist_base : nullptr,
+                          p->any_feat ? feat_base : nullptr, workspace};
     bool same = p->exec != nullptr;
     for (int q = 0; q < 4 && same; ++q) same = key[q] == p->key[q];
     if (!same) {

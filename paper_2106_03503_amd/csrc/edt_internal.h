@@ -128,15 +128,20 @@ __host__ __device__ inline int items_near(int H, int W) {
 // Phases of the transform, in launch order.
 enum Phase { kPhBits = 0, kPhCarry = 1, kPhCompact = 2, kPhNear = 3, kPhRows = 4, kPhases = 5 };
 
-// One image of a batch, as offsets from the bases passed at submission.
+// One image of a batch, as offsets from the bases passed at submission (a
+// base may be 0, and the offsets then absolute addresses).
 struct BatchImage {
     int64_t mask_off;  // bytes from the mask base
     int64_t mpitch;    // bytes between mask rows
-    int64_t out_off;   // elements from the output bases
+    int64_t dist_off;  // elements from the distance base
+    int64_t feat_off;  // elements from the feature base
     int64_t opitch;    // elements between output rows
     int64_t ws_off;    // bytes from the workspace base
-    int32_t H, W, pol, want_feat;
+    int32_t H, W, pol;
+    int32_t outs;      // kOutDist | kOutFeat: the outputs this image writes
 };
+constexpr int32_t kOutDist = 1;
+constexpr int32_t kOutFeat = 2;
 
 // Device table of a batch: images, then for each phase the exclusive prefix
 // of work items over the images (nimg + 1 entries), and the bases.
@@ -144,21 +149,25 @@ struct BatchTable {
     const BatchImage* img;
     const int32_t* prefix[kPhases];
     int nimg;
-    const uint8_t* mask_base;
-    int32_t* dist_base;  // may be null
-    int32_t* feat_base;  // may be null
-    uint8_t* ws_base;
+    uintptr_t mask_base;
+    uintptr_t dist_base;
+    uintptr_t feat_base;
+    uintptr_t ws_base;
 };
 
 __device__ inline Img batch_img(const BatchTable& t, int im) {
     const BatchImage b = t.img[im];
     Img g;
-    g.mask = t.mask_base + b.mask_off;
+    g.mask = reinterpret_cast<const uint8_t*>(t.mask_base + (uintptr_t)b.mask_off);
     g.mpitch = b.mpitch;
-    g.dist = t.dist_base ? t.dist_base + b.out_off : nullptr;
-    g.feat = (t.feat_base && b.want_feat) ? t.feat_base + b.out_off : nullptr;
+    g.dist = (b.outs & kOutDist)
+                 ? reinterpret_cast<int32_t*>(t.dist_base + 4 * (uintptr_t)b.dist_off)
+                 : nullptr;
+    g.feat = (b.outs & kOutFeat)
+                 ? reinterpret_cast<int32_t*>(t.feat_base + 4 * (uintptr_t)b.feat_off)
+                 : nullptr;
     g.opitch = b.opitch;
-    g.ws = t.ws_base + b.ws_off;
+    g.ws = reinterpret_cast<uint8_t*>(t.ws_base + (uintptr_t)b.ws_off);
     g.H = b.H;
     g.W = b.W;
     g.pol = b.pol;
@@ -178,6 +187,24 @@ __device__ inline int batch_image_of(const BatchTable& t, int p, int item) {
     }
     return a;
 }
+
+// Batch tables (host side).  A table occupies table_bytes(n) bytes: the n
+// BatchImage rows, then per phase the n + 1 prefix entries, each part 256-byte
+// aligned.  pack_table writes it to host memory `dst` (images' H, W fields
+// set) and returns the work totals per phase and the widest image;
+// EDT_ERR_TOO_LARGE if a total does not fit int32.  table_view points a
+// BatchTable at a copy of it in device memory.
+size_t table_bytes(int n);
+int32_t pack_table(const BatchImage* img, int n, uint8_t* dst, int* totals, int* max_w);
+BatchTable table_view(const uint8_t* dev_table, int n);
+// The whole transform of a batch, enqueued on stream.
+hipError_t enqueue_batch(const BatchTable& t, const int* totals, int max_w, hipStream_t stream);
+// Argument checks of one image (shared by the single, batch and serving calls).
+int32_t check_image(const uint8_t* mask, int32_t H, int32_t W, int64_t mask_pitch,
+                    int32_t polarity, int32_t metric, int64_t out_pitch);
+// Enqueue the transform of one image (arguments already checked).
+hipError_t enqueue_single(const Img& g, hipStream_t stream);
+bool prof_enabled();
 
 // Kernel timing (edt_profile_begin / edt_profile_end): a token from
 // prof_begin (negative when timing is off) is closed by prof_end.

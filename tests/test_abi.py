@@ -114,3 +114,41 @@ def test_batch_plan_validation_before_any_device_call(edt):
     assert plan([D(0, 16, 0, 16, 8, 16, 5, 1)]) == -1          # polarity
     assert plan([D(-16, 16, 0, 16, 8, 16, 0, 1)]) == -1        # negative offset
     assert _lib.lib.edt_plan_destroy(None) == -1
+
+
+def test_serve_validation_before_any_device_call(edt):
+    import ctypes
+    from paper_2106_03503_amd import _lib
+    lib = _lib.lib
+    C = _lib.ServeConfig
+    fake = 0x100000  # 256-byte aligned, never dereferenced
+    srv = ctypes.c_void_p()
+
+    def create(cfg, arena=fake, nbytes=1 << 30):
+        return lib.edt_serve_create(ctypes.byref(cfg) if cfg is not None else None, arena,
+                                    nbytes, ctypes.byref(srv))
+
+    assert create(None) == -1
+    assert create(C(0, 0, 1, 0)) == -1                  # max_inflight
+    assert create(C(0, 8, 0, 0)) == -1                  # n_streams
+    assert create(C(0, 8, 17, 0)) == -1                 # n_streams above the limit
+    assert create(C(0, 8, 1, 1025)) == -1               # max_group above the limit
+    assert create(C(0, 8, 1, 0), arena=fake + 64) == -1  # misaligned arena
+    assert create(C(0, 8, 1, 0), arena=None) == -1
+    assert create(C(2 << 30, 8, 1, 0)) == -1            # budget above the arena
+    assert create(C(4096, 8, 1, 0)) == -1               # budget below the launch tables
+    assert srv.value is None
+    # reserved bytes: 2 * n_streams tables
+    r1 = _lib.Server.reserved_bytes(1, 16)
+    assert r1 > 0 and r1 % 256 == 0
+    assert _lib.Server.reserved_bytes(2, 16) == 2 * r1
+    assert _lib.Server.reserved_bytes(1, 1024) > r1
+    assert _lib.Server.reserved_bytes(0, 16) == 0
+    # null server handles
+    t = ctypes.c_uint64()
+    done = ctypes.c_int32()
+    assert lib.edt_serve_submit(None, None, ctypes.byref(t)) == -1
+    assert lib.edt_serve_poll(None, 1, ctypes.byref(done)) == -1
+    assert lib.edt_serve_wait(None, 1, 0) == -1
+    assert lib.edt_serve_stats(None, None) == -1
+    assert lib.edt_serve_destroy(None) == -1
