@@ -22,18 +22,20 @@ int32_t pack_table(const BatchImage* img, int n, uint8_t* dst, int* totals, int*
     const size_t img_bytes = align_up(sizeof(BatchImage) * (size_t)n, 256);
     const size_t pre_bytes = align_up(sizeof(int32_t) * ((size_t)n + 1), 256);
     memcpy(dst, img, sizeof(BatchImage) * (size_t)n);
-    int64_t acc[kPhases] = {0, 0, 0, 0, 0};
+    int64_t acc[kPhases] = {};
     int mw = 0;
     for (int q = 0; q < n; ++q) {
         const int H = img[q].H, W = img[q].W;
-        const int64_t items[kPhases] = {items_bits(H, W), items_carry(H, W), 1, items_near(H, W), H};
+        const bool lanes = takes_lanes(W);
+        const int64_t items[kPhases] = {items_bits(H, W), items_carry(H, W), 1, items_near(H, W),
+                                        lanes ? 0 : H, lanes ? items_lanes(H) : 0};
         for (int p = 0; p < kPhases; ++p) {
             int32_t* pre = reinterpret_cast<int32_t*>(dst + img_bytes + p * pre_bytes);
             pre[q] = (int32_t)acc[p];
             acc[p] += items[p];
             if (acc[p] > INT32_MAX) return EDT_ERR_TOO_LARGE;
         }
-        if (W > mw) mw = W;
+        if (!lanes && W > mw) mw = W;
     }
     for (int p = 0; p < kPhases; ++p) {
         reinterpret_cast<int32_t*>(dst + img_bytes + p * pre_bytes)[n] = (int32_t)acc[p];
@@ -57,7 +59,8 @@ BatchTable table_view(const uint8_t* dev_table, int n) {
 
 hipError_t enqueue_batch(const BatchTable& t, const int* totals, int max_w, hipStream_t s) {
     hipError_t e = launch_column_pass_batch(t, totals, s);
-    if (e == hipSuccess) e = launch_row_pass_batch(t, totals, max_w, s);
+    if (e == hipSuccess && totals[kPhRows] > 0) e = launch_row_pass_batch(t, totals, max_w, s);
+    if (e == hipSuccess && totals[kPhLanes] > 0) e = launch_row_lanes_batch(t, totals[kPhLanes], s);
     return e;
 }
 
@@ -68,7 +71,7 @@ struct edt_plan {
     int want_dist = 1;
     int any_feat = 0;
     int max_w = 0;
-    int totals[edt::kPhases] = {0, 0, 0, 0, 0};
+    int totals[edt::kPhases] = {};
     size_t ws_bytes = 0;
     int device = 0;
     void* table = nullptr;  // device copy of the batch table

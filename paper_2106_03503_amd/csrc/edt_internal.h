@@ -125,8 +125,25 @@ __host__ __device__ inline int items_near(int H, int W) {
     return ((H + kBand - 1) / kBand) * ((W + kNearCols - 1) / kNearCols);
 }
 
-// Phases of the transform, in launch order.
-enum Phase { kPhBits = 0, kPhCarry = 1, kPhCompact = 2, kPhNear = 3, kPhRows = 4, kPhases = 5 };
+// Row pass with one lane per row: rows per work item (one wavefront), stack
+// entries per lane kept in LDS, and the widest image of a batch that takes it.
+constexpr int kLaneRows = 64;
+constexpr int kLaneRing = 32;
+constexpr int kLaneMaxW = 2048;
+__host__ __device__ inline int items_lanes(int H) { return (H + kLaneRows - 1) / kLaneRows; }
+__host__ __device__ inline bool takes_lanes(int W) { return W <= kLaneMaxW; }
+
+// Phases of the transform, in launch order (a batch image's rows are work
+// items of kPhRows, or row groups of kPhLanes when takes_lanes(W)).
+enum Phase {
+    kPhBits = 0,
+    kPhCarry = 1,
+    kPhCompact = 2,
+    kPhNear = 3,
+    kPhRows = 4,
+    kPhLanes = 5,
+    kPhases = 6
+};
 
 // One image of a batch, as offsets from the bases passed at submission (a
 // base may be 0, and the offsets then absolute addresses).
@@ -155,19 +172,27 @@ struct BatchTable {
     uintptr_t ws_base;
 };
 
+// A device address as a pointer into global memory.  Going through the
+// global address space lets the compiler emit global (not flat) loads and
+// stores for everything derived from it; a flat access also counts as an
+// LDS access, so every wait for LDS data would wait for memory as well.
+template <typename T>
+__device__ __forceinline__ T* global_ptr(uintptr_t a) {
+    typedef __attribute__((address_space(1))) T GT;
+    return (T*)(GT*)a;
+}
+
 __device__ inline Img batch_img(const BatchTable& t, int im) {
     const BatchImage b = t.img[im];
     Img g;
-    g.mask = reinterpret_cast<const uint8_t*>(t.mask_base + (uintptr_t)b.mask_off);
+    g.mask = global_ptr<const uint8_t>(t.mask_base + (uintptr_t)b.mask_off);
     g.mpitch = b.mpitch;
-    g.dist = (b.outs & kOutDist)
-                 ? reinterpret_cast<int32_t*>(t.dist_base + 4 * (uintptr_t)b.dist_off)
-                 : nullptr;
-    g.feat = (b.outs & kOutFeat)
-                 ? reinterpret_cast<int32_t*>(t.feat_base + 4 * (uintptr_t)b.feat_off)
-                 : nullptr;
+    g.dist = (b.outs & kOutDist) ? global_ptr<int32_t>(t.dist_base + 4 * (uintptr_t)b.dist_off)
+                                 : nullptr;
+    g.feat = (b.outs & kOutFeat) ? global_ptr<int32_t>(t.feat_base + 4 * (uintptr_t)b.feat_off)
+                                 : nullptr;
     g.opitch = b.opitch;
-    g.ws = reinterpret_cast<uint8_t*>(t.ws_base + (uintptr_t)b.ws_off);
+    g.ws = global_ptr<uint8_t>(t.ws_base + (uintptr_t)b.ws_off);
     g.H = b.H;
     g.W = b.W;
     g.pol = b.pol;
@@ -191,7 +216,8 @@ __device__ inline int batch_image_of(const BatchTable& t, int p, int item) {
 // Batch tables (host side).  A table occupies table_bytes(n) bytes: the n
 // BatchImage rows, then per phase the n + 1 prefix entries, each part 256-byte
 // aligned.  pack_table writes it to host memory `dst` (images' H, W fields
-// set) and returns the work totals per phase and the widest image;
+// set) and returns the work totals per phase and the widest image that the
+// row pass takes with several lanes per row;
 // EDT_ERR_TOO_LARGE if a total does not fit int32.  table_view points a
 // BatchTable at a copy of it in device memory.
 size_t table_bytes(int n);
@@ -233,6 +259,7 @@ hipError_t launch_row_pass(const Img& g, uint8_t* slots, hipStream_t stream);
 hipError_t launch_column_pass_batch(const BatchTable& t, const int* totals, hipStream_t stream);
 hipError_t launch_row_pass_batch(const BatchTable& t, const int* totals, int max_w,
                                  hipStream_t stream);
+hipError_t launch_row_lanes_batch(const BatchTable& t, int total, hipStream_t stream);
 hipError_t launch_sqrt(const int32_t* D, float* out, int64_t n, hipStream_t stream);
 
 }  // namespace edt

@@ -1,0 +1,324 @@
+// Horizontal pass with one lane per row, for batches (Section 3.3 of Strutz,
+// arXiv 2106.03503: the lower envelope of the parabolas of Eq. eq_parabola,
+// built with one left-to-right scan and a stack, then one more pass over the
+// row to fill it).
+//
+// A wavefront takes 64 consecutive rows of one image and every lane runs the
+// paper's scan on its own row, so no lane waits for another and there are no
+// barriers: the candidate columns are the same for every row, only their site
+// rows differ, so all lanes step through the candidates together and differ
+// only in how many parabolas they pop.  The order of parabolas and the start
+// of a new one are exactly those of the several-lanes-per-row pass: pixels
+// compare lexicographically on (D, feature index), and parabola l takes over
+// from k at floor((N - [l wins ties]) / (2 (l - k))) + 1 with N from Eq.
+// eq_intersection.
+//
+// Where the stack lives: the top entries in registers and an LDS ring; older
+// entries in memory, entry e (packed column and site row) at slot e of the
+// row's own output and its start at slot e of the row's list of site rows,
+// which the scan has already read there (e never exceeds the index of the
+// candidate being scanned).  Once every lane has finished, the wavefront
+// fills the rows one by one: a row's whole envelope is copied into LDS before
+// any of its pixels is written.
+#include "edt_internal.h"
+
+namespace edt {
+namespace {
+
+constexpr int R = kLaneRing;
+constexpr int kBlk = 32;  // candidates per load of site rows (64 bytes per lane)
+
+// LDS of one wavefront: the scan keeps the top R stack entries of every lane
+// here; the fill then reuses the space for one row's whole envelope.
+union LaneLds {
+    struct {
+        uint32_t c[R][kLaneRows];  // packed candidate (column << 16 | site row)
+        int16_t s[R][kLaneRows];   // first pixel it owns
+    } ring;
+    struct {
+        uint32_t c[kLaneMaxW];
+        int16_t s[kLaneMaxW];
+    } row;
+};
+
+__device__ __forceinline__ int sqr(int x) { return x * x; }
+
+// floor(num / den) + 1, clamped to [0, W], for den >= 2 and num < 2^31: a
+// float estimate of the quotient (relative error below 2^-21, so within one
+// of the floor wherever the result is below W), corrected with the integer
+// remainder.
+__device__ __forceinline__ int start_at(int num, int den, int W) {
+    if (num < 0) return 0;
+    const float qf = (float)num * __builtin_amdgcn_rcpf((float)den);
+    int q = (int)qf;
+    if (q > W) return W;
+    const int r = num - q * den;
+    if (r < 0)
+        --q;
+    else if (r >= den)
+        ++q;
+    return min(q + 1, W);
+}
+
+typedef int v4i __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ void put4(int32_t* __restrict__ p, int j, int W, bool vec, int v0,
+                                     int v1, int v2, int v3) {
+    if (vec && j + 4 <= W) {
+        const v4i v = {v0, v1, v2, v3};
+        __builtin_nontemporal_store(v, reinterpret_cast<v4i*>(p + j));
+    } else {
+        __builtin_nontemporal_store(v0, p + j);
+        if (j + 1 < W) __builtin_nontemporal_store(v1, p + j + 1);
+        if (j + 2 < W) __builtin_nontemporal_store(v2, p + j + 2);
+        if (j + 3 < W) __builtin_nontemporal_store(v3, p + j + 3);
+    }
+}
+
+// Last index e in [lo, hi) with st[e] <= j, given st[lo] <= j.
+__device__ __forceinline__ int last_at_or_before(const int16_t* st, int lo, int hi, int j) {
+    int a = lo, b = hi - 1;
+    while (a < b) {
+        const int mid = (a + b + 1) >> 1;
+        if (st[mid] <= j)
+            a = mid;
+        else
+            b = mid - 1;
+    }
+    return a;
+}
+
+// Move ring block [b, b + 16) of this lane to memory (ranks b..b+15 of
+// (sc, rr)); b is a multiple of 16.
+__device__ __forceinline__ void spill_block(int b, uint32_t* sc, int16_t* rr, bool vec,
+                                            LaneLds& sh, int lane) {
+    uint32_t c[16];
+    uint32_t sp[8];
+#pragma unroll
+    for (int k = 0; k < 16; ++k) c[k] = sh.ring.c[(b + k) % R][lane];
+#pragma unroll
+    for (int k = 0; k < 8; ++k)
+        sp[k] = (uint32_t)(uint16_t)sh.ring.s[(b + 2 * k) % R][lane] |
+                ((uint32_t)(uint16_t)sh.ring.s[(b + 2 * k + 1) % R][lane] << 16);
+    if (vec) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+            *reinterpret_cast<int4*>(sc + b + 4 * k) =
+                make_int4((int)c[4 * k], (int)c[4 * k + 1], (int)c[4 * k + 2], (int)c[4 * k + 3]);
+    } else {
+#pragma unroll
+        for (int k = 0; k < 16; ++k) sc[b + k] = c[k];
+    }
+    *reinterpret_cast<int4*>(rr + b) = make_int4((int)sp[0], (int)sp[1], (int)sp[2], (int)sp[3]);
+    *reinterpret_cast<int4*>(rr + b + 8) = make_int4((int)sp[4], (int)sp[5], (int)sp[6], (int)sp[7]);
+}
+
+// Bring block [b, b + 16) of this lane back from memory into the ring.
+__device__ __forceinline__ void fill_block(int b, const uint32_t* sc, const int16_t* rr, bool vec,
+                                           LaneLds& sh, int lane) {
+    uint32_t c[16];
+    if (vec) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const int4 x = *reinterpret_cast<const int4*>(sc + b + 4 * k);
+            c[4 * k] = (uint32_t)x.x;
+            c[4 * k + 1] = (uint32_t)x.y;
+            c[4 * k + 2] = (uint32_t)x.z;
+            c[4 * k + 3] = (uint32_t)x.w;
+        }
+    } else {
+#pragma unroll
+        for (int k = 0; k < 16; ++k) c[k] = sc[b + k];
+    }
+    const int4 s0 = *reinterpret_cast<const int4*>(rr + b);
+    const int4 s1 = *reinterpret_cast<const int4*>(rr + b + 8);
+    const uint32_t sp[8] = {(uint32_t)s0.x, (uint32_t)s0.y, (uint32_t)s0.z, (uint32_t)s0.w,
+                            (uint32_t)s1.x, (uint32_t)s1.y, (uint32_t)s1.z, (uint32_t)s1.w};
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+        sh.ring.c[(b + k) % R][lane] = c[k];
+        sh.ring.s[(b + k) % R][lane] = (int16_t)(sp[k >> 1] >> (16 * (k & 1)));
+    }
+}
+
+// Scan of row i (this lane's row): builds the row's envelope as a stack and
+// leaves it in memory, entry e at rank e of (sc, rr); returns its size.  The
+// top two entries stay in registers and the ranks [base, M) in an LDS ring of
+// two 16-entry blocks; a full ring moves its older block to memory in one
+// piece, and a pop below the ring brings a block back, so the loop touches
+// memory in whole 64- and 32-byte pieces and waits for it only when it reads
+// the next 32 site rows or, rarely, brings a block back.
+__device__ int scan_row(const int i, const int n, const int W, const int16_t* __restrict__ cols,
+                        int16_t* rr, uint32_t* sc, const bool vec, LaneLds& sh, const int lane) {
+    int M = 0, base = 0;
+    int colA = 0, rowA = 0, gA = 0, sA = 0;  // top entry (M - 1)
+    uint32_t cB = 0;                         // entry below it (M - 2)
+    int sB = 0;
+    for (int q0 = 0; q0 < n; q0 += kBlk) {
+        static_assert(kBlk == 32, "four 16-byte loads of site rows per block");
+        const int4 rv0 = *reinterpret_cast<const int4*>(rr + q0);
+        const int4 rv1 = *reinterpret_cast<const int4*>(rr + q0 + 8);
+        const int4 rv2 = *reinterpret_cast<const int4*>(rr + q0 + 16);
+        const int4 rv3 = *reinterpret_cast<const int4*>(rr + q0 + 24);
+        const int4 cv0 = *reinterpret_cast<const int4*>(cols + q0);
+        const int4 cv1 = *reinterpret_cast<const int4*>(cols + q0 + 8);
+        const int4 cv2 = *reinterpret_cast<const int4*>(cols + q0 + 16);
+        const int4 cv3 = *reinterpret_cast<const int4*>(cols + q0 + 24);
+        const int cnt = min(kBlk, n - q0);
+        for (int k = 0; k < kBlk / 8; ++k) {
+            if (8 * k >= cnt) break;
+            const int4 r4 = k == 0 ? rv0 : k == 1 ? rv1 : k == 2 ? rv2 : rv3;
+            const int4 c4 = k == 0 ? cv0 : k == 1 ? cv1 : k == 2 ? cv2 : cv3;
+            const uint32_t rw[4] = {(uint32_t)r4.x, (uint32_t)r4.y, (uint32_t)r4.z, (uint32_t)r4.w};
+            const uint32_t cw[4] = {(uint32_t)c4.x, (uint32_t)c4.y, (uint32_t)c4.z, (uint32_t)c4.w};
+#pragma unroll
+            for (int u8 = 0; u8 < 8; ++u8) {
+                const int u = 8 * k + u8;
+                if (u >= cnt) break;
+                const int row = (int)((rw[u8 >> 1] >> (16 * (u8 & 1))) & 0xFFFFu);
+                const int col = (int)((cw[u8 >> 1] >> (16 * (u8 & 1))) & 0xFFFFu);
+                const int gC = sqr(i - row);
+                // pop every parabola that the new one beats where it starts
+                while (M > 0) {
+                    const int dC = gC + sqr(sA - col), dA = gA + sqr(sA - colA);
+                    if (!(dC < dA || (dC == dA && row < rowA))) break;
+                    --M;
+                    if (M > 0) {
+                        colA = (int)(cB >> 16);
+                        rowA = (int)(cB & 0xFFFFu);
+                        gA = sqr(i - rowA);
+                        sA = sB;
+                    }
+                    if (M > 1) {
+                        const int e = M - 2;
+                        if (e < base) {  // below the ring: bring its block back
+                            base -= 16;
+                            fill_block(base, sc, rr, vec, sh, lane);
+                        }
+                        cB = sh.ring.c[e % R][lane];
+                        sB = sh.ring.s[e % R][lane];
+                    }
+                }
+                int s = 0;
+                if (M > 0) {
+                    const int dC = gC + sqr(W - 1 - col), dA = gA + sqr(W - 1 - colA);
+                    if (!(dC < dA || (dC == dA && row < rowA))) continue;  // never wins in the row
+                    s = start_at(gC - gA + (col - colA) * (col + colA) - (row < rowA ? 1 : 0),
+                                 2 * (col - colA), W);
+                    cB = ((uint32_t)colA << 16) | (uint32_t)rowA;
+                    sB = sA;
+                }
+                if (M - base == R) {  // ring full: its older block goes to memory
+                    spill_block(base, sc, rr, vec, sh, lane);
+                    base += 16;
+                }
+                sh.ring.c[M % R][lane] = ((uint32_t)col << 16) | (uint32_t)row;
+                sh.ring.s[M % R][lane] = (int16_t)s;
+                colA = col;
+                rowA = row;
+                gA = gC;
+                sA = s;
+                ++M;
+            }
+        }
+    }
+    for (int e = base; e < M; ++e) {  // the rest of the stack to memory
+        sc[e] = sh.ring.c[e % R][lane];
+        rr[e] = sh.ring.s[e % R][lane];
+    }
+    return M;
+}
+
+// Work item = 64 consecutive rows of one image of the batch: every lane scans
+// its own row, then the wavefront fills the rows one after another, each from
+// its envelope copied into LDS, four adjacent pixels per lane and store.
+__global__ __launch_bounds__(kLaneRows) void k_row_lanes_batch(BatchTable tb) {
+    __shared__ LaneLds sh;
+    __shared__ int s_m[kLaneRows];
+    const int item = blockIdx.x;
+    const int im = batch_image_of(tb, kPhLanes, item);
+    const Img g = batch_img(tb, im);
+    const int lane = threadIdx.x;
+    const int i0 = (item - tb.prefix[kPhLanes][im]) * kLaneRows;
+    const int rows = min(kLaneRows, g.H - i0);
+    const Views v = views_of(g);
+    const int n = v.meta[0];
+    const int pitch = v.meta[1];
+    const int W = g.W;
+    int32_t* base = g.dist ? g.dist : g.feat;  // holds the stacks until the fill
+    const bool vec = (!g.dist || reinterpret_cast<uintptr_t>(g.dist) % 16 == 0) &&
+                     (!g.feat || reinterpret_cast<uintptr_t>(g.feat) % 16 == 0) &&
+                     (g.opitch % 4 == 0);
+    if (n > 0 && lane < rows) {
+        const int i = i0 + lane;
+        s_m[lane] = scan_row(i, n, W, v.cols, v.rc + (int64_t)i * pitch,
+                             reinterpret_cast<uint32_t*>(base + (int64_t)i * g.opitch), vec, sh,
+                             lane);
+    }
+    __syncthreads();  // stacks in memory are complete; the ring is free
+
+    for (int r = 0; r < rows; ++r) {
+        const int i = i0 + r;
+        int32_t* drow = g.dist ? g.dist + (int64_t)i * g.opitch : nullptr;
+        int32_t* frow = g.feat ? g.feat + (int64_t)i * g.opitch : nullptr;
+        const int M = n > 0 ? s_m[r] : 0;
+        const uint32_t* sc = reinterpret_cast<const uint32_t*>(base + (int64_t)i * g.opitch);
+        const int16_t* rr = v.rc + (int64_t)i * pitch;
+        for (int e = lane; e < M; e += kLaneRows) {
+            sh.row.c[e] = sc[e];
+            sh.row.s[e] = rr[e];
+        }
+        __syncthreads();
+        int e = 0;
+        for (int j = 4 * lane; j < W; j += 4 * kLaneRows) {
+            int d[4], f[4];
+            if (M == 0) {
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    d[q] = INT32_MAX;
+                    f[q] = -1;
+                }
+            } else {
+                // owner of pixel j: the last entry starting at or before it,
+                // searched from this lane's previous owner
+                int step = 1;
+                while (e + step < M && sh.row.s[e + step] <= j) {
+                    e += step;
+                    step <<= 1;
+                }
+                e = last_at_or_before(sh.row.s, e, min(M, e + step), j);
+                uint32_t c = sh.row.c[e];
+                int nst = e + 1 < M ? sh.row.s[e + 1] : INT32_MAX;
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int jj = j + q;
+                    d[q] = 0;
+                    f[q] = 0;
+                    if (jj < W) {
+                        while (jj >= nst) {
+                            ++e;
+                            c = sh.row.c[e];
+                            nst = e + 1 < M ? sh.row.s[e + 1] : INT32_MAX;
+                        }
+                        const int col = (int)(c >> 16), row = (int)(c & 0xFFFFu);
+                        d[q] = sqr(i - row) + sqr(jj - col);
+                        f[q] = row * W + col;
+                    }
+                }
+            }
+            if (drow) put4(drow, j, W, vec, d[0], d[1], d[2], d[3]);
+            if (frow) put4(frow, j, W, vec, f[0], f[1], f[2], f[3]);
+        }
+        __syncthreads();  // the next row reuses the LDS copy
+    }
+}
+
+}  // namespace
+
+hipError_t launch_row_lanes_batch(const BatchTable& tb, int total, hipStream_t stream) {
+    if (total < 1) return hipSuccess;
+    EDT_LAUNCH_AS("k_row_lanes", k_row_lanes_batch, dim3(total), dim3(kLaneRows), 0, stream, tb);
+    return hipGetLastError();
+}
+
+}  // namespace edt

@@ -99,3 +99,36 @@ def test_batch_equals_single_image_calls(edt):
         assert torch.equal(plan.image(D, q), Ds)
         assert torch.equal(plan.image(F, q), Fs)
     plan.close()
+
+
+def _deep_pop_mask(H, W, seed):
+    """Rows whose envelopes grow long and are then mostly popped at once: in
+    each row band the site rows drift away slowly from left to right (every
+    parabola survives), then a column with a site in the band itself hides
+    dozens of them, more than the 32 stack entries a lane keeps in LDS."""
+    rng = np.random.default_rng(seed)
+    m = np.zeros((H, W), np.uint8)
+    for c in range(W):
+        if c % 97 == 96:
+            m[rng.integers(0, H, 8), c] = 1  # near sites: deep pops
+        else:
+            m[min(H - 1, (c % 97) // 2), c] = 1  # slowly drifting sites
+    return m
+
+
+def test_lane_rows_deep_pops_and_ties(edt):
+    """The one-lane-per-row pass: stacks deeper than its LDS ring, pops that
+    reach below it, tie-heavy regular grids, and sizes that leave partial
+    row groups and partial 4-pixel stores."""
+    rng = np.random.default_rng(11)
+    imgs = []
+    for k, (H, W) in enumerate([(130, 700), (64, 1000), (65, 333), (200, 257), (7, 4096)]):
+        imgs.append((_deep_pop_mask(H, W, k), k % 2, True))
+    for k, (H, W, step) in enumerate([(96, 301, 6), (129, 513, 4), (70, 998, 10)]):
+        m = np.zeros((H, W), np.uint8)
+        m[::step, ::step] = 1  # equidistant sites everywhere: ties
+        imgs.append((m, 0, True))
+        imgs.append((1 - m, 1, True))
+    for (H, W) in [(1, 1), (1, 4096), (4096, 1), (3, 5), (64, 64)]:
+        imgs.append(((rng.random((H, W)) < 0.3).astype(np.uint8), 0, True))
+    _check_batch(edt, imgs, submits=2)
