@@ -129,7 +129,7 @@ __host__ __device__ inline int items_near(int H, int W) {
 // entries per lane kept in LDS, and the widest image of a batch that takes it.
 constexpr int kLaneRows = 64;
 constexpr int kLaneRing = 32;
-constexpr int kLaneMaxW = 2048;
+constexpr int kLaneMaxW = 1024;
 __host__ __device__ inline int items_lanes(int H) { return (H + kLaneRows - 1) / kLaneRows; }
 __host__ __device__ inline bool takes_lanes(int W) { return W <= kLaneMaxW; }
 

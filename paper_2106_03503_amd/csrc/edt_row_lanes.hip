@@ -257,18 +257,39 @@ __global__ __launch_bounds__(kLaneRows) void k_row_lanes_batch(BatchTable tb) {
     }
     __syncthreads();  // stacks in memory are complete; the ring is free
 
+    // the envelope of row r + 1 is in flight while row r is filled
+    constexpr int kPer = kLaneMaxW / kLaneRows;  // entries per lane
+    uint32_t pc[kPer];
+    int16_t ps[kPer];
+    auto fetch = [&](int r) {
+        const int Mr = n > 0 ? s_m[r] : 0;
+        const uint32_t* sc = reinterpret_cast<const uint32_t*>(base + (int64_t)(i0 + r) * g.opitch);
+        const int16_t* rr = v.rc + (int64_t)(i0 + r) * pitch;
+#pragma unroll
+        for (int k = 0; k < kPer; ++k) {
+            const int e = lane + k * kLaneRows;
+            if (e < Mr) {
+                pc[k] = sc[e];
+                ps[k] = rr[e];
+            }
+        }
+    };
+    if (rows > 0) fetch(0);
     for (int r = 0; r < rows; ++r) {
         const int i = i0 + r;
         int32_t* drow = g.dist ? g.dist + (int64_t)i * g.opitch : nullptr;
         int32_t* frow = g.feat ? g.feat + (int64_t)i * g.opitch : nullptr;
         const int M = n > 0 ? s_m[r] : 0;
-        const uint32_t* sc = reinterpret_cast<const uint32_t*>(base + (int64_t)i * g.opitch);
-        const int16_t* rr = v.rc + (int64_t)i * pitch;
-        for (int e = lane; e < M; e += kLaneRows) {
-            sh.row.c[e] = sc[e];
-            sh.row.s[e] = rr[e];
+#pragma unroll
+        for (int k = 0; k < kPer; ++k) {
+            const int e = lane + k * kLaneRows;
+            if (e < M) {
+                sh.row.c[e] = pc[k];
+                sh.row.s[e] = ps[k];
+            }
         }
         __syncthreads();
+        if (r + 1 < rows) fetch(r + 1);
         int e = 0;
         for (int j = 4 * lane; j < W; j += 4 * kLaneRows) {
             int d[4], f[4];
