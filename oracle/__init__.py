@@ -70,6 +70,8 @@ def bind(path: str):
     lib.oracle_sqrt_f32.restype = None
     lib.oracle_brute_metric.argtypes = [P, i32, i32, i64, i32, i32, P, P]
     lib.oracle_brute_metric.restype = i64
+    lib.oracle_cityblock_scans.argtypes = [P, i32, i32, i64, i32, i32, P]
+    lib.oracle_cityblock_scans.restype = None
     return lib
 
 
@@ -199,3 +201,13 @@ def brute_metric(mask, metric: int, polarity: int = 0):
     F = np.empty((H, W), np.int32)
     _load().oracle_brute_metric(_ptr(m), H, W, W, polarity, metric, _ptr(D), _ptr(F))
     return D, F
+
+
+def cityblock_scans(mask, polarity: int = 0, stages: int = 4):
+    """City-block distances by the four propagation scans of Section 2.2
+    (stages=2: only the two column scans, the vertical distances)."""
+    m = _mask(mask)
+    H, W = m.shape
+    D = np.empty((H, W), np.int32)
+    _load().oracle_cityblock_scans(_ptr(m), H, W, W, polarity, stages, _ptr(D))
+    return D

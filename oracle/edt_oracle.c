@@ -39,6 +39,9 @@
  *                        (Section 3.1), in fp64 then rounded to fp32.
  *   oracle_brute_metric  O1 for the city-block (e=1) and chessboard (e=inf)
  *                        members of the Minkowski family (Eq. eq_Minkowski).
+ *   oracle_cityblock_scans  the city-block transform by the four propagation
+ *                        scans of Section 2.2 (columns down and up, then rows
+ *                        forward and backward, one comparison per pixel each).
  *
  * Integer arithmetic is done in int64 throughout; nothing here is tuned.
  */
@@ -505,4 +508,44 @@ int64_t oracle_brute_metric(const uint8_t *mask, int32_t H, int32_t W,
     }
     free(s);
     return n;
+}
+
+/* City-block distance transform by the four one-comparison scans of Section
+ * 2.2: initialise sites with 0 and every other pixel with a value above any
+ * possible distance; then in every column a downward scan (d(i,j) > d(i-1,j)+1
+ * lowers d(i,j)) and an upward scan (same with d(i+1,j)); then in every row a
+ * forward scan (with d(i,j-1)) and a backward scan (with d(i,j+1)).  stages = 2
+ * stops after the two column scans (the vertical distances of Figure
+ * fig_cityblockDTparallel(b)), stages = 4 runs all four.  Cells that keep the
+ * initial value (no site reachable) come out as INT32_MAX. */
+void oracle_cityblock_scans(const uint8_t *mask, int32_t H, int32_t W, int64_t pitch,
+                            int32_t polarity, int32_t stages, int32_t *D)
+{
+    const int64_t big = (int64_t)H + W; /* above (H-1) + (W-1) */
+    int64_t *d = (int64_t *)malloc(sizeof(int64_t) * (size_t)H * (size_t)W);
+    for (int32_t i = 0; i < H; ++i)
+        for (int32_t j = 0; j < W; ++j)
+            d[(int64_t)i * W + j] = is_site(mask[(int64_t)i * pitch + j], polarity) ? 0 : big;
+    for (int32_t j = 0; j < W; ++j) {
+        for (int32_t i = 1; i < H; ++i) { /* downward */
+            int64_t *c = &d[(int64_t)i * W + j], up = d[(int64_t)(i - 1) * W + j];
+            if (*c > up + 1) *c = up + 1;
+        }
+        for (int32_t i = H - 2; i >= 0; --i) { /* upward */
+            int64_t *c = &d[(int64_t)i * W + j], dn = d[(int64_t)(i + 1) * W + j];
+            if (*c > dn + 1) *c = dn + 1;
+        }
+    }
+    if (stages >= 4) {
+        for (int32_t i = 0; i < H; ++i) {
+            int64_t *row = &d[(int64_t)i * W];
+            for (int32_t j = 1; j < W; ++j) /* forward */
+                if (row[j] > row[j - 1] + 1) row[j] = row[j - 1] + 1;
+            for (int32_t j = W - 2; j >= 0; --j) /* backward */
+                if (row[j] > row[j + 1] + 1) row[j] = row[j + 1] + 1;
+        }
+    }
+    for (int64_t q = 0; q < (int64_t)H * W; ++q)
+        D[q] = d[q] >= big ? ORACLE_INF_SQ : (int32_t)d[q];
+    free(d);
 }

@@ -10,6 +10,7 @@ import pytest
 
 import oracle
 from tests import test_oracle as T
+from tests import test_oracle_metrics as TM
 
 MUTANTS = [
     ("tie rule reversed", "l_wins_tie = fl < fk;", "l_wins_tie = fl > fk;"),
@@ -43,6 +44,15 @@ MUTANTS = [
     ("basic row pass ignores the feature on ties",
      "if (best < 0 || d < best || (d == best && f < bestf)) {",
      "if (best < 0 || d < best) {"),
+    ("city-block scans skip the upward column scan",
+     "for (int32_t i = H - 2; i >= 0; --i) { /* upward */",
+     "for (int32_t i = H - 2; i >= H; --i) { /* upward */"),
+    ("city-block scans step by 2", "if (*c > up + 1) *c = up + 1;", "if (*c > up + 2) *c = up + 2;"),
+    ("city-block scans skip the backward row scan",
+     "for (int32_t j = W - 2; j >= 0; --j) /* backward */",
+     "for (int32_t j = W - 2; j >= W; --j) /* backward */"),
+    ("chessboard takes the smaller offset", "(di > dj ? di : dj)", "(di < dj ? di : dj)"),
+    ("city-block squares the offsets", "? di + dj :", "? di * di + dj * dj :"),
 ]
 
 
@@ -65,6 +75,15 @@ def _pins():
     yield T.test_sites_in_one_row_reduce_to_1d, ()
     yield T.test_invariants_on_generated_masks, ()
     yield T.test_sqrt_epilogue, ()
+    for pol in (0, 1):
+        yield TM.test_cityblock_definition_matches_figure, (pol,)
+        yield TM.test_chessboard_definition_matches_figure, (pol,)
+    yield TM.test_cityblock_scans_vertical_stage_matches_figure, ()
+    yield TM.test_cityblock_final_matches_figure_but_the_erratum, ()
+    for seed in range(4):
+        yield TM.test_cityblock_scans_equal_definition, (seed,)
+    for metric in (1, 2):
+        yield TM.test_metric_closed_forms_and_invariants, (metric,)
 
 
 def _failures(lib):
