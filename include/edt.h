@@ -52,7 +52,7 @@ extern "C" {
 typedef int32_t edt_status;
 #define EDT_OK 0
 #define EDT_ERR_INVALID_ARG (-1)   /* null pointer, bad pitch, bad enum, short workspace */
-#define EDT_ERR_UNSUPPORTED (-2)   /* a metric this build does not provide */
+#define EDT_ERR_UNSUPPORTED (-2)   /* a metric (or metric + output) not provided */
 #define EDT_ERR_TOO_LARGE (-3)     /* H or W outside [1, EDT_MAX_SIDE] */
 #define EDT_ERR_OUT_OF_MEMORY (-4) /* a host or library-owned allocation failed */
 #define EDT_ERR_BUSY (-5)          /* a server's memory budget or queue is full */
@@ -62,7 +62,14 @@ typedef int32_t edt_status;
 #define EDT_TO_OBJECT 0
 #define EDT_TO_BACKGROUND 1
 
+/* Metrics of the Minkowski family (Eq. eq_Minkowski, Section 1.3.1).  For the
+ * squared Euclidean metric dist_sq holds d^2; for city-block (e = 1, d = |di| +
+ * |dj|) and chessboard (e = infinity, d = max(|di|, |dj|)) it holds d itself.
+ * The chamfer 4-3 approximation (Section 2.2) is reserved. */
 #define EDT_METRIC_EUCLIDEAN_SQ 0
+#define EDT_METRIC_CITYBLOCK 1
+#define EDT_METRIC_CHESSBOARD 2
+#define EDT_METRIC_CHAMFER34 3
 
 #define EDT_INF_SQ INT32_MAX /* dist_sq where the image has no site */
 #define EDT_NO_SITE (-1)     /* feature where the image has no site */
@@ -79,12 +86,16 @@ const char *edt_status_string(edt_status s);
  * W is outside [1, EDT_MAX_SIDE]. */
 size_t edt_workspace_bytes(int32_t H, int32_t W, int32_t want_feature);
 
-/* Exact squared Euclidean distance transform (Section 3: the vertical pass of
- * Section 3.1, then per row the lower envelope of parabolas of Section 3.3.1,
- * Eq. eq_parabola and Eq. eq_intersection).
+/* Exact distance transform: squared Euclidean (Section 3: the vertical pass
+ * of Section 3.1, then per row the lower envelope of parabolas of Section
+ * 3.3.1, Eq. eq_parabola and Eq. eq_intersection), or city-block / chessboard
+ * (the same two passes with the row costs |j - k| + |i - r| and max(|j - k|,
+ * |i - r|) in place of the parabolas; equal to the propagation scans of
+ * Section 2.1 for city-block).
  *   mask        device, uint8, H x W with row pitch mask_pitch bytes
  *   polarity    EDT_TO_OBJECT or EDT_TO_BACKGROUND
- *   metric      EDT_METRIC_EUCLIDEAN_SQ (anything else: EDT_ERR_UNSUPPORTED)
+ *   metric      EDT_METRIC_EUCLIDEAN_SQ, _CITYBLOCK or _CHESSBOARD
+ *               (_CHAMFER34: EDT_ERR_UNSUPPORTED; other values: INVALID_ARG)
  *   dist_sq     device, int32, H x W with row pitch out_pitch elements; written
  *   workspace   device, at least edt_workspace_bytes(H, W, 0) bytes, 256-byte
  *               aligned; contents on entry are ignored and on exit undefined
@@ -94,9 +105,11 @@ edt_status edt_sq(const uint8_t *mask, int32_t H, int32_t W, int64_t mask_pitch,
                   int64_t out_pitch, void *workspace, size_t workspace_bytes,
                   void *stream);
 
-/* Exact squared distance plus feature transform (the nearest site's index,
- * Section 3.3 "keep track of which column contributes the minimum", extended
- * with the site's row from the vertical pass).  Same arguments as edt_sq, plus
+/* Exact distance plus feature transform (the nearest site's index, Section
+ * 3.3: the column that gives the minimum, extended with the site's row from
+ * the vertical pass), for the squared Euclidean and the city-block metric
+ * (chessboard: EDT_ERR_UNSUPPORTED, because its ties between sites of one
+ * column are not decided by the vertical pass).  Same arguments as edt_sq, plus
  *   dist_sq     may be NULL when only the features are wanted
  *   feature     device, int32, H x W with row pitch out_pitch elements; written */
 edt_status edt_feature(const uint8_t *mask, int32_t H, int32_t W,

@@ -204,7 +204,7 @@ def brute_metric(mask, metric: int, polarity: int = 0):
 
 
 def cityblock_scans(mask, polarity: int = 0, stages: int = 4):
-    """City-block distances by the four propagation scans of Section 2.2
+    """City-block distances by the four propagation scans of Section 2.1
     (stages=2: only the two column scans, the vertical distances)."""
     m = _mask(mask)
     H, W = m.shape

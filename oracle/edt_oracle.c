@@ -40,7 +40,7 @@
  *   oracle_brute_metric  O1 for the city-block (e=1) and chessboard (e=inf)
  *                        members of the Minkowski family (Eq. eq_Minkowski).
  *   oracle_cityblock_scans  the city-block transform by the four propagation
- *                        scans of Section 2.2 (columns down and up, then rows
+ *                        scans of Section 2.1 (columns down and up, then rows
  *                        forward and backward, one comparison per pixel each).
  *
  * Integer arithmetic is done in int64 throughout; nothing here is tuned.
@@ -511,7 +511,7 @@ int64_t oracle_brute_metric(const uint8_t *mask, int32_t H, int32_t W,
 }
 
 /* City-block distance transform by the four one-comparison scans of Section
- * 2.2: initialise sites with 0 and every other pixel with a value above any
+ * 2.1: initialise sites with 0 and every other pixel with a value above any
  * possible distance; then in every column a downward scan (d(i,j) > d(i-1,j)+1
  * lowers d(i,j)) and an upward scan (same with d(i+1,j)); then in every row a
  * forward scan (with d(i,j-1)) and a backward scan (with d(i,j+1)).  stages = 2

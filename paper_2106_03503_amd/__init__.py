@@ -13,6 +13,9 @@ transform runs in the library's HIP kernels; there is no fallback.
 """
 from ._lib import (  # noqa: F401
     EDT_INF_SQ,
+    EDT_METRIC_CHESSBOARD,
+    EDT_METRIC_CITYBLOCK,
+    EDT_METRIC_EUCLIDEAN_SQ,
     EDT_NO_SITE,
     EDT_TO_BACKGROUND,
     EDT_TO_OBJECT,

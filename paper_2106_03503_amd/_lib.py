@@ -15,6 +15,9 @@ EDT_OK = 0
 EDT_TO_OBJECT = 0
 EDT_TO_BACKGROUND = 1
 EDT_METRIC_EUCLIDEAN_SQ = 0
+EDT_METRIC_CITYBLOCK = 1
+EDT_METRIC_CHESSBOARD = 2
+EDT_METRIC_CHAMFER34 = 3
 EDT_INF_SQ = 2**31 - 1
 EDT_NO_SITE = -1
 
@@ -123,7 +126,8 @@ def _workspace(H, W, want_feature, device, workspace):
 def sq(mask: torch.Tensor, polarity: int = EDT_TO_OBJECT, metric: int = EDT_METRIC_EUCLIDEAN_SQ,
        out: torch.Tensor | None = None, workspace: torch.Tensor | None = None,
        stream=None) -> torch.Tensor:
-    """Squared Euclidean distance of every pixel to the nearest site (int32)."""
+    """Distance of every pixel to the nearest site (int32): squared Euclidean
+    (metric 0), city-block (1) or chessboard (2)."""
     mask = _check_mask(mask)
     H, W = mask.shape
     out = _check_out(out, H, W, mask.device, "out")

@@ -32,10 +32,8 @@ edt_status check_image(const uint8_t* mask, int32_t H, int32_t W, int64_t mask_p
     if (H < 1 || W < 1 || H > EDT_MAX_SIDE || W > EDT_MAX_SIDE) return EDT_ERR_TOO_LARGE;
     if (!mask || mask_pitch < W || out_pitch < W) return EDT_ERR_INVALID_ARG;
     if (polarity != EDT_TO_OBJECT && polarity != EDT_TO_BACKGROUND) return EDT_ERR_INVALID_ARG;
-    if (metric != EDT_METRIC_EUCLIDEAN_SQ) {
-        if (metric < 0 || metric > 3) return EDT_ERR_INVALID_ARG;
-        return EDT_ERR_UNSUPPORTED;
-    }
+    if (metric < 0 || metric > EDT_METRIC_CHAMFER34) return EDT_ERR_INVALID_ARG;
+    if (metric == EDT_METRIC_CHAMFER34) return EDT_ERR_UNSUPPORTED;
     return EDT_OK;
 }
 
@@ -46,6 +44,9 @@ static edt_status run(const uint8_t* mask, int32_t H, int32_t W, int64_t mask_pi
     edt_status st = check_image(mask, H, W, mask_pitch, polarity, metric, out_pitch);
     if (st != EDT_OK) return st;
     if (!dist && !feat) return EDT_ERR_INVALID_ARG;
+    // chessboard ties can sit at other rows of a column than its nearest site,
+    // which the vertical pass does not keep: no exact feature transform
+    if (feat && metric == EDT_METRIC_CHESSBOARD) return EDT_ERR_UNSUPPORTED;
     const Layout L = layout_for(H, W);
     if (!workspace || workspace_bytes < L.total) return EDT_ERR_INVALID_ARG;
     if ((reinterpret_cast<uintptr_t>(workspace) & 255) != 0) return EDT_ERR_INVALID_ARG;
@@ -60,6 +61,7 @@ static edt_status run(const uint8_t* mask, int32_t H, int32_t W, int64_t mask_pi
     g.H = H;
     g.W = W;
     g.pol = polarity;
+    g.metric = metric;
     return enqueue_single(g, s) == hipSuccess ? EDT_OK : EDT_ERR_DEVICE;
 }
 

@@ -90,6 +90,7 @@ struct Img {
     int64_t opitch;    // elements between output rows
     uint8_t* ws;       // this image's workspace (layout_for(H, W))
     int H, W, pol;
+    int metric;        // EDT_METRIC_*: 0 squared Euclidean, 1 city-block, 2 chessboard
 };
 
 // Pointers into an image's workspace.
@@ -196,6 +197,7 @@ __device__ inline Img batch_img(const BatchTable& t, int im) {
     g.H = b.H;
     g.W = b.W;
     g.pol = b.pol;
+    g.metric = 0;
     return g;
 }
 

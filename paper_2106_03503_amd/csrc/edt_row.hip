@@ -3,6 +3,13 @@
 // (Eq. eq_parabola) over the columns k that hold a site (the same list for
 // every row), then every pixel is filled from the parabola that owns it.
 //
+// The same pass serves the city-block and chessboard metrics: the parabola of
+// column k is replaced by |i - r_k| + |j - k| or max(|i - r_k|, |j - k|), for
+// which, as for parabolas, a column right of another beats it on a suffix of
+// the row (their difference never falls as j grows), so the envelope, the
+// merges and the fill are unchanged and only the cost and the first winning
+// pixel differ.
+//
 // Order and ties: parabolas are compared at a pixel lexicographically on
 // (D, feature index), feature = r*W + k, so every pixel is owned by its nearest
 // site with the smallest row-major index.  For columns k < l, parabola l beats
@@ -36,31 +43,63 @@ namespace {
 __device__ __forceinline__ int ccol(uint32_t c) { return (int)(c >> 16); }
 __device__ __forceinline__ int crow(uint32_t c) { return (int)(c & 0xFFFFu); }
 
-// Squared distance from pixel (i, j) to the site of candidate C (< 2^31 for
-// sides up to 32767).
-__device__ __forceinline__ int parab(uint32_t C, int i, int j) {
+// Distance from pixel (i, j) to the site of candidate C under metric kM: the
+// squared Euclidean distance (kM = 0, below 2^31 for sides up to 32767), the
+// city-block distance (1) or the chessboard distance (2).
+template <int kM>
+__device__ __forceinline__ int dist_to(uint32_t C, int i, int j) {
     const int dr = i - crow(C), dc = j - ccol(C);
-    return dr * dr + dc * dc;
+    if (kM == 0) return dr * dr + dc * dc;
+    const int ar = dr < 0 ? -dr : dr, ac = dc < 0 ? -dc : dc;
+    return kM == 1 ? ar + ac : max(ar, ac);
 }
 
 // Does B (a column right of A's) beat A at pixel j of row i?
+template <int kM>
 __device__ __forceinline__ bool beats(uint32_t B, uint32_t A, int i, int j) {
-    const int fb = parab(B, i, j), fa = parab(A, i, j);
+    const int fb = dist_to<kM>(B, i, j), fa = dist_to<kM>(A, i, j);
     return fb < fa || (fb == fa && crow(B) < crow(A));
 }
 
-// First pixel j in [0, W] from which B beats A (W: never inside the row).
-// B beats A at j iff j*den > num, or j*den == num and B has the smaller index
-// (a smaller site row: B's column is larger), with num and den from Eq.
-// eq_intersection; so j >= floor((num - [B wins ties]) / den) + 1.
+// First pixel j in [0, W] from which B beats A (W: never inside the row); B
+// beats A on a suffix of the row under each metric.
+//   Euclidean: B beats A at j iff j*den > num, or j*den == num and B has the
+//   smaller index (a smaller site row: B's column is larger), with num and den
+//   from Eq. eq_intersection; so j >= floor((num - [B wins ties]) / den) + 1.
+//   City-block: with vertical offsets fa, fb, B wins left of both columns iff
+//   fb + l < fa + k (ties by index), right of both iff fb - l < fa - k, and in
+//   between from the first j with 2j > fb - fa + l + k.
+//   Chessboard: the suffix is found by bisection.
+template <int kM>
 __device__ __forceinline__ int first_win(uint32_t A, uint32_t B, int i, int W) {
     const int k = ccol(A), l = ccol(B), rk = crow(A), rl = crow(B);
-    const int dk = (i - rk) * (i - rk), dl = (i - rl) * (i - rl);
-    const int num = dl - dk + (l - k) * (l + k);
-    const int n2 = num - (rl < rk ? 1 : 0);
-    if (n2 < 0) return 0;
-    const unsigned q = (unsigned)n2 / (2u * (unsigned)(l - k));
-    return q + 1u < (unsigned)W ? (int)q + 1 : W;
+    const int t = rl < rk ? 1 : 0;  // B wins ties
+    if (kM == 0) {
+        const int dk = (i - rk) * (i - rk), dl = (i - rl) * (i - rl);
+        const int num = dl - dk + (l - k) * (l + k);
+        const int n2 = num - t;
+        if (n2 < 0) return 0;
+        const unsigned q = (unsigned)n2 / (2u * (unsigned)(l - k));
+        return q + 1u < (unsigned)W ? (int)q + 1 : W;
+    } else if (kM == 1) {
+        const int fk = i > rk ? i - rk : rk - i, fl = i > rl ? i - rl : rl - i;
+        const int a = fk + k, b = fl + l;
+        if (b < a || (b == a && t)) return 0;
+        const int ra = fk - k, rb = fl - l;
+        if (!(rb < ra || (rb == ra && t))) return W;
+        const int j = ((fl - fk + l + k - t) >> 1) + 1;  // floor division by 2
+        return min(max(j, 0), W);
+    } else {
+        int lo = 0, hi = W;
+        while (lo < hi) {
+            const int mid = (lo + hi) >> 1;
+            if (beats<kM>(B, A, i, mid))
+                hi = mid;
+            else
+                lo = mid + 1;
+        }
+        return lo;
+    }
 }
 
 // Chunk slots: logical slot l = t*S + u (slot u of lane t's chunk) is stored
@@ -80,7 +119,7 @@ struct Slots {
 // [lo, hi), nxt/prv link the non-empty chunks of a group, gf/gl hold the first
 // and last non-empty chunk of the group starting at c.  The first survivor of
 // a group always starts at pixel 0.
-template <int T, int S>
+template <int kM, int T, int S>
 __device__ void merge_groups(int g_l, int g_r, const Slots<T, S>& sl,
                              int16_t* __restrict__ lo, int16_t* __restrict__ hi,
                              int16_t* __restrict__ nxt, int16_t* __restrict__ prv,
@@ -98,7 +137,7 @@ __device__ void merge_groups(int g_l, int g_r, const Slots<T, S>& sl,
     bool left_alive = true, right_alive = true;
     for (;;) {
         const uint32_t A = sl.c(ia), B = sl.c(ib);
-        if (beats(B, A, i, sl.s(ia))) {  // A is hidden wherever it owned pixels
+        if (beats<kM>(B, A, i, sl.s(ia))) {  // A is hidden wherever it owned pixels
             if (ia > lo[ca]) {
                 --ia;
                 continue;
@@ -119,7 +158,7 @@ __device__ void merge_groups(int g_l, int g_r, const Slots<T, S>& sl,
             const int cn = nxt[cb];
             bend = cn >= 0 ? sl.s(lo[cn]) : W;
         }
-        if (!beats(B, A, i, bend - 1)) {  // B is hidden wherever it owned pixels
+        if (!beats<kM>(B, A, i, bend - 1)) {  // B is hidden wherever it owned pixels
             if (ib + 1 < hi[cb]) {
                 ++ib;
                 continue;
@@ -133,7 +172,7 @@ __device__ void merge_groups(int g_l, int g_r, const Slots<T, S>& sl,
             ib = lo[cb];
             continue;
         }
-        sl.s(ib) = (int16_t)first_win(A, B, i, W);  // the seam
+        sl.s(ib) = (int16_t)first_win<kM>(A, B, i, W);  // the seam
         break;
     }
     if (left_alive && right_alive) {
@@ -217,7 +256,7 @@ __device__ __forceinline__ bool form_takes(int n, int W) {
     return n > kSparseMaxN && W > T * S / 2 && W <= T * S;
 }
 
-template <int T, int S, bool kSparse, bool kGlobal>
+template <int kM, int T, int S, bool kSparse, bool kGlobal>
 __device__ void process_rows(const Img& g, int i0, int i1, int di,
                              RowLds<T, S, kSparse, kGlobal>& sh, uint8_t* gslot) {
     constexpr int NW = T / 64;
@@ -280,12 +319,12 @@ __device__ void process_rows(const Img& g, int i0, int i1, int di,
             bool keep = true;
             while (m > 0) {
                 const uint32_t A = sl.c(base + m - 1);
-                if (beats(C, A, i, sl.s(base + m - 1))) {  // C hides the stack top
+                if (beats<kM>(C, A, i, sl.s(base + m - 1))) {  // C hides the stack top
                     --m;
                     continue;
                 }
-                keep = beats(C, A, i, W - 1);  // C wins somewhere inside the row
-                if (keep) sl.s(base + m) = (int16_t)first_win(A, C, i, W);
+                keep = beats<kM>(C, A, i, W - 1);  // C wins somewhere inside the row
+                if (keep) sl.s(base + m) = (int16_t)first_win<kM>(A, C, i, W);
                 break;
             }
             if (m == 0) {
@@ -307,7 +346,7 @@ __device__ void process_rows(const Img& g, int i0, int i1, int di,
         // 3. merge up the tree
         for (int w = 1; w < nchunks; w <<= 1) {
             if ((t & (2 * w - 1)) == 0 && t + w < nchunks)
-                merge_groups<T, S>(t, t + w, sl, sh.lo, sh.hi, sh.nxt, sh.prv, sh.gf, sh.gl, i, W);
+                merge_groups<kM, T, S>(t, t + w, sl, sh.lo, sh.hi, sh.nxt, sh.prv, sh.gf, sh.gl, i, W);
             __syncthreads();
         }
         // 4. survivors to the front of the list, in column order (plain layout)
@@ -371,7 +410,7 @@ __device__ void process_rows(const Img& g, int i0, int i1, int di,
                             C = cand[e];
                             nst = e + 1 < M ? st[e + 1] : INT32_MAX;
                         }
-                        d[q] = parab(C, i, jj);
+                        d[q] = dist_to<kM>(C, i, jj);
                         f[q] = crow(C) * W + ccol(C);
                     } else {
                         d[q] = 0;
@@ -387,11 +426,11 @@ __device__ void process_rows(const Img& g, int i0, int i1, int di,
 }
 
 // One image: rows blockIdx.x, blockIdx.x + gridDim.x, ...
-template <int T, int S, bool kSparse, bool kGlobal>
+template <int kM, int T, int S, bool kSparse, bool kGlobal>
 __global__ __launch_bounds__(T) void k_row_single(Img g, uint8_t* __restrict__ slots) {
     __shared__ RowLds<T, S, kSparse, kGlobal> sh;
     uint8_t* gslot = kGlobal ? slots + (size_t)blockIdx.x * wide_slot_bytes() : nullptr;
-    process_rows<T, S, kSparse, kGlobal>(g, blockIdx.x, g.H, gridDim.x, sh, gslot);
+    process_rows<kM, T, S, kSparse, kGlobal>(g, blockIdx.x, g.H, gridDim.x, sh, gslot);
 }
 
 // A batch: workgroup g takes the contiguous run of row items
@@ -412,7 +451,7 @@ __global__ __launch_bounds__(T) void k_row_batch(BatchTable tb, int total) {
         const Img g = batch_img(tb, im);
         const int r0 = item - tb.prefix[kPhRows][im];
         const int r1 = min(g.H, end - tb.prefix[kPhRows][im]);
-        process_rows<T, S, kSparse, false>(g, r0, r1, 1, sh, nullptr);
+        process_rows<0, T, S, kSparse, false>(g, r0, r1, 1, sh, nullptr);
         item += r1 - r0;
     }
 }
@@ -426,15 +465,15 @@ int blocks_per_cu(K kernel, int threads) {
     return nb;
 }
 
-template <int T, int S, bool kSparse, bool kGlobal>
+template <int kM, int T, int S, bool kSparse, bool kGlobal>
 hipError_t launch_single(const Img& g, uint8_t* slots, hipStream_t stream) {
     static int per_cu = 0;
-    if (per_cu == 0) per_cu = blocks_per_cu(k_row_single<T, S, kSparse, kGlobal>, T);
+    if (per_cu == 0) per_cu = blocks_per_cu(k_row_single<kM, T, S, kSparse, kGlobal>, T);
     int grid = per_cu * device_cus();
     if (kGlobal && grid > kWideSlots) grid = kWideSlots;
     if (grid > g.H) grid = g.H;
     const char* name = kSparse ? "k_row_sparse" : (kGlobal ? "k_row_dense_global" : "k_row_dense");
-    EDT_LAUNCH_AS(name, (k_row_single<T, S, kSparse, kGlobal>), dim3(grid), dim3(T), 0, stream,
+    EDT_LAUNCH_AS(name, (k_row_single<kM, T, S, kSparse, kGlobal>), dim3(grid), dim3(T), 0, stream,
                   g, slots);
     return hipGetLastError();
 }
@@ -451,19 +490,26 @@ hipError_t launch_batch(const BatchTable& tb, int total, hipStream_t stream) {
     return hipGetLastError();
 }
 
+template <int kM>
+hipError_t launch_rows_metric(const Img& g, uint8_t* slots, hipStream_t stream) {
+    // Both forms are enqueued; each returns at once unless the image's number
+    // of candidate columns (known only on the device) is in its range.
+    hipError_t e = launch_single<kM, kSparseLanes, kRowS, true, false>(g, slots, stream);
+    const int W = g.W;
+    if (e != hipSuccess || W <= kSparseMaxN) return e;
+    if (W <= 2048) return launch_single<kM, 128, kRowS, false, false>(g, slots, stream);
+    if (W <= 4096) return launch_single<kM, 256, kRowS, false, false>(g, slots, stream);
+    if (W <= 8192) return launch_single<kM, 512, kRowS, false, false>(g, slots, stream);
+    if (W <= kLdsMaxW) return launch_single<kM, 1024, kRowS, false, false>(g, slots, stream);
+    return launch_single<kM, 1024, 2 * kRowS, false, true>(g, slots, stream);
+}
+
 }  // namespace
 
 hipError_t launch_row_pass(const Img& g, uint8_t* slots, hipStream_t stream) {
-    // Both forms are enqueued; each returns at once unless the image's number
-    // of candidate columns (known only on the device) is in its range.
-    hipError_t e = launch_single<kSparseLanes, kRowS, true, false>(g, slots, stream);
-    const int W = g.W;
-    if (e != hipSuccess || W <= kSparseMaxN) return e;
-    if (W <= 2048) return launch_single<128, kRowS, false, false>(g, slots, stream);
-    if (W <= 4096) return launch_single<256, kRowS, false, false>(g, slots, stream);
-    if (W <= 8192) return launch_single<512, kRowS, false, false>(g, slots, stream);
-    if (W <= kLdsMaxW) return launch_single<1024, kRowS, false, false>(g, slots, stream);
-    return launch_single<1024, 2 * kRowS, false, true>(g, slots, stream);
+    if (g.metric == 1) return launch_rows_metric<1>(g, slots, stream);
+    if (g.metric == 2) return launch_rows_metric<2>(g, slots, stream);
+    return launch_rows_metric<0>(g, slots, stream);
 }
 
 hipError_t launch_row_pass_batch(const BatchTable& tb, const int* totals, int max_w,

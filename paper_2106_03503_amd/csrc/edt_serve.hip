@@ -128,6 +128,7 @@ edt::Img image_of(const edt_server* s, const Req& q) {
     g.H = q.r.H;
     g.W = q.r.W;
     g.pol = q.r.polarity;
+    g.metric = EDT_METRIC_EUCLIDEAN_SQ;
     return g;
 }
 

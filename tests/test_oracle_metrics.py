@@ -2,7 +2,7 @@
 (Eq. eq_Minkowski): city-block (e = 1) and chessboard (e = infinity).
 
 The brute-force definition is pinned by the distance tables the paper prints
-from a centre pixel, and the four-scan city-block transform of Section 2.2 by
+from a centre pixel, and the four-scan city-block transform of Section 2.1 by
 the tables of its worked example; the two are then checked against each other
 on random masks, where the scans share nothing with the definition."""
 import numpy as np
