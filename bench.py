@@ -43,7 +43,7 @@ PATH_BYTES_PER_PX = 13.0  # 1 mask + 2 + 2 intermediate + 4 D + 4 F
 def algo_bytes(kernel: str, H: int, W: int, n: int, with_dist: bool = True) -> int:
     """Algorithmic HBM bytes of one launch of `kernel` on an H x W image whose
     sites occupy n columns: what the kernel must read and write at minimum
-    given its inputs and outputs ('Measurement')."""
+    given its inputs and outputs."""
     nb = (H + 63) // 64
     if kernel == "k_band_bits":          # mask in, one site bit per pixel out
         return H * W + nb * W * 8
@@ -102,10 +102,22 @@ def make_mask(name):
     raise SystemExit(f"unknown workload {name}")
 
 
-def kernel_source_hash() -> str:
+# Source files that define each kernel (its own file and the shared header).
+KERNEL_SOURCES = {
+    "k_band_bits": ("edt_column.hip",), "k_band_carry": ("edt_column.hip",),
+    "k_col_compact": ("edt_column.hip",), "k_nearest_row": ("edt_column.hip",),
+    "k_row_sparse": ("edt_row.hip",), "k_row_dense": ("edt_row.hip",),
+    "k_row_dense_global": ("edt_row.hip",), "k_row_lanes": ("edt_row_lanes.hip",),
+    "k_sqrt": ("edt_api.hip",),
+}
+
+
+def kernel_source_hash(kernel: str) -> str:
+    """Hash of the sources of `kernel`: counters taken before a change to them
+    no longer describe it."""
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2106_03503_amd", "csrc")
-    for f in sorted(os.listdir(csrc)):
+    for f in KERNEL_SOURCES.get(kernel, tuple(sorted(os.listdir(csrc)))) + ("edt_internal.h",):
         with open(os.path.join(csrc, f), "rb") as fh:
             h.update(f.encode() + fh.read())
     return h.hexdigest()[:16]
@@ -113,7 +125,7 @@ def kernel_source_hash() -> str:
 
 def traffic_from_profiles(kernel: str, workload: str):
     """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
-    summary, or None when the kernels changed since it was taken."""
+    summary, or None when the kernel's sources changed since it was taken."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     try:
         with open(path) as f:
@@ -121,7 +133,7 @@ def traffic_from_profiles(kernel: str, workload: str):
     except (OSError, ValueError):
         return None
     ent = t.get("kernels", {}).get(workload, {}).get(kernel)
-    if not ent or t.get("source_hash") != kernel_source_hash():
+    if not ent or ent.get("source_hash") != kernel_source_hash(kernel):
         return None
     return ent.get("bytes_per_launch")
 
@@ -269,7 +281,9 @@ def run_batch(args):
             if fn(*c) != 0:
                 raise RuntimeError("edt_feature failed")
 
-    ms_single, _ = timed(per_image, max(2, args.steps // 5), 1, profile=False)
+    ms_single = None
+    if not args.no_per_image:
+        ms_single, _ = timed(per_image, max(2, args.steps // 5), 1, profile=False)
 
     ns = [site_columns(m, p) for m, p in imgs]
     out = base_line(args, px / (ms * 1e-3) / 1e9, ms,
@@ -278,9 +292,10 @@ def run_batch(args):
     out["roofline"] = roofline(
         kt, lambda k: sum(algo_bytes(k, m.shape[0], m.shape[1], n) for (m, _), n in zip(imgs, ns)),
         args.workload)
-    out["per_image"] = {"value": round(px / (ms_single * 1e-3) / 1e9, 3),
-                        "ms_per_step": round(ms_single, 4), "call": "edt_feature per image"}
-    out["batched_over_per_image"] = round(ms_single / ms, 2)
+    if ms_single is not None:
+        out["per_image"] = {"value": round(px / (ms_single * 1e-3) / 1e9, 3),
+                            "ms_per_step": round(ms_single, 4), "call": "edt_feature per image"}
+        out["batched_over_per_image"] = round(ms_single / ms, 2)
     out["kernels_ms_per_step"] = {k: round(v[1] / max(3, args.steps // 4), 4)
                                   for k, v in sorted(kt.items())}
     if not args.no_cpu:
@@ -386,6 +401,8 @@ def main():
     ap.add_argument("--budget-gib", type=float, default=16.0, help="serve: memory budget")
     ap.add_argument("--streams", type=int, default=4, help="serve: server streams")
     ap.add_argument("--no-cpu", action="store_true", help="skip the cpu_baseline leg")
+    ap.add_argument("--no-per-image", action="store_true",
+                    help="batch2048: skip the per-image edt_feature leg")
     ap.add_argument("--copy-calibration", action="store_true")
     args = ap.parse_args()
 
