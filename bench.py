@@ -10,7 +10,8 @@ Workloads (--workload):
                        256^2 Bernoulli(0.01));
   batch2048            one step = one edt_batch_submit over 2048 images of
                        uneven size (sides 64..1024, 5-60 ellipses, mixed
-                       polarity), replayed as a captured graph; the same
+                       polarity), replayed as a captured graph, after
+                       edt_batch_autotune picked the schedule; the same
                        images launched one by one through edt_feature are
                        timed beside it ("per_image").
   serve                one step = one replay of a Poisson request stream
@@ -259,6 +260,11 @@ def run_batch(args):
     stream = torch.cuda.current_stream()
     px = sum(m.size for m, _ in imgs)
 
+    tune = None
+    if not args.no_autotune:
+        cands, chosen = plan.autotune(mask, D, F, workspace=ws, stream=stream)
+        tune = {"candidates": cands, "chosen": chosen}
+
     def step():
         plan.submit(mask, D, F, workspace=ws, stream=stream)
 
@@ -298,6 +304,8 @@ def run_batch(args):
         out["batched_over_per_image"] = round(ms_single / ms, 2)
     out["kernels_ms_per_step"] = {k: round(v[1] / max(3, args.steps // 4), 4)
                                   for k, v in sorted(kt.items())}
+    if tune is not None:
+        out["autotune"] = tune
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(imgs, px)
     plan.close()
@@ -403,6 +411,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the cpu_baseline leg")
     ap.add_argument("--no-per-image", action="store_true",
                     help="batch2048: skip the per-image edt_feature leg")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="batch2048: keep the default schedule instead of autotuning it")
     ap.add_argument("--copy-calibration", action="store_true")
     args = ap.parse_args()
 

@@ -169,7 +169,30 @@ edt_status edt_batch_submit(edt_plan *plan, const uint8_t *mask_base, int32_t *d
                             int32_t *feat_base, void *workspace, size_t workspace_bytes,
                             void *stream);
 
-/* Release a plan (its device table and graphs).  Work already enqueued with
+/* Result of edt_batch_autotune (host struct). */
+#define EDT_TUNE_MAX 8
+typedef struct {
+    int32_t tried;                       /* candidate schedules timed */
+    int32_t chosen;                      /* index of the one kept */
+    int32_t lane_w[EDT_TUNE_MAX];        /* widest image rowed one lane per row */
+    int32_t largest_first[EDT_TUNE_MAX]; /* images listed by decreasing size */
+    float ms[EDT_TUNE_MAX];              /* best of three timed submissions */
+} edt_tune_report;
+
+/* Autotune the plan's schedule on these buffers (same arguments as
+ * edt_batch_submit; the outputs are written, with the same values, by every
+ * candidate).  Candidates: which widths take the one-lane-per-row row pass
+ * (none, up to 256, up to 1024, as the batch's widths make them differ) and
+ * whether images are listed largest first, so that the longest work items
+ * start first.  Each is run once untimed and three times timed with HIP events
+ * on `stream` (this call waits for them); the fastest is kept for later
+ * submissions.  report (host) may be NULL.  Results never depend on the
+ * schedule. */
+edt_status edt_batch_autotune(edt_plan *plan, const uint8_t *mask_base, int32_t *dist_base,
+                              int32_t *feat_base, void *workspace, size_t workspace_bytes,
+                              void *stream, edt_tune_report *report);
+
+/* Release a plan (its device tables and graphs).  Work already enqueued with
  * it must have completed. */
 edt_status edt_plan_destroy(edt_plan *plan);
 

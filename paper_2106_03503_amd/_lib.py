@@ -199,8 +199,16 @@ class ImageDesc(ctypes.Structure):
                 ("polarity", ctypes.c_int32), ("want_feature", ctypes.c_int32)]
 
 
+class TuneReport(ctypes.Structure):
+    _fields_ = [("tried", ctypes.c_int32), ("chosen", ctypes.c_int32),
+                ("lane_w", ctypes.c_int32 * 8), ("largest_first", ctypes.c_int32 * 8),
+                ("ms", ctypes.c_float * 8)]
+
+
 def _bind_batch():
     P, i32, sz = ctypes.c_void_p, ctypes.c_int32, ctypes.c_size_t
+    _lib.edt_batch_autotune.argtypes = [P, P, P, P, P, sz, P, P]
+    _lib.edt_batch_autotune.restype = i32
     _lib.edt_batch_plan.argtypes = [P, i32, i32, P, P]
     _lib.edt_batch_plan.restype = i32
     _lib.edt_batch_submit.argtypes = [P, P, P, P, P, sz, P]
@@ -279,6 +287,24 @@ class BatchPlan:
                                      workspace.numel() * workspace.element_size(),
                                      _stream_ptr(stream)), "edt_batch_submit")
         return workspace
+
+    def autotune(self, mask_flat, dist_flat=None, feat_flat=None, workspace=None, stream=None):
+        """Time the candidate schedules on these buffers and keep the fastest;
+        returns [{lane_w, largest_first, ms}, ...] and the chosen index."""
+        if workspace is None:
+            workspace = torch.empty(max(self.workspace_bytes, 1), dtype=torch.uint8,
+                                    device=mask_flat.device)
+        rep = TuneReport()
+        _check(_lib.edt_batch_autotune(self._plan, mask_flat.data_ptr(),
+                                       dist_flat.data_ptr() if dist_flat is not None else None,
+                                       feat_flat.data_ptr() if feat_flat is not None else None,
+                                       workspace.data_ptr(),
+                                       workspace.numel() * workspace.element_size(),
+                                       _stream_ptr(stream), ctypes.byref(rep)),
+               "edt_batch_autotune")
+        cands = [{"lane_w": rep.lane_w[q], "largest_first": bool(rep.largest_first[q]),
+                  "ms": round(float(rep.ms[q]), 4)} for q in range(rep.tried)]
+        return cands, int(rep.chosen)
 
     def close(self):
         if self._plan:

@@ -2,10 +2,14 @@
 // phase of the transform runs as one persistent launch over a device table of
 // the images, instead of one launch per phase per image, and a submission with
 // the same buffers as the previous one replays a captured HIP graph of those
-// launches.
+// launches.  How the work is laid out (which widths take the one-lane-per-row
+// row pass, and whether the images are listed largest first so that the
+// longest work items start first) is a schedule; edt_batch_autotune times the
+// candidate schedules on the caller's buffers and keeps the fastest.
 #include "../../include/edt.h"
 #include "edt_internal.h"
 
+#include <algorithm>
 #include <cstdlib>
 #include <cstring>
 #include <new>
@@ -18,7 +22,8 @@ size_t table_bytes(int n) {
            kPhases * align_up(sizeof(int32_t) * ((size_t)n + 1), 256);
 }
 
-int32_t pack_table(const BatchImage* img, int n, uint8_t* dst, int* totals, int* max_w) {
+int32_t pack_table(const BatchImage* img, int n, int lane_w, uint8_t* dst, int* totals,
+                   int* max_w) {
     const size_t img_bytes = align_up(sizeof(BatchImage) * (size_t)n, 256);
     const size_t pre_bytes = align_up(sizeof(int32_t) * ((size_t)n + 1), 256);
     memcpy(dst, img, sizeof(BatchImage) * (size_t)n);
@@ -26,7 +31,7 @@ int32_t pack_table(const BatchImage* img, int n, uint8_t* dst, int* totals, int*
     int mw = 0;
     for (int q = 0; q < n; ++q) {
         const int H = img[q].H, W = img[q].W;
-        const bool lanes = takes_lanes(W);
+        const bool lanes = W <= lane_w;
         const int64_t items[kPhases] = {items_bits(H, W), items_carry(H, W), 1, items_near(H, W),
                                         lanes ? 0 : H, lanes ? items_lanes(H) : 0};
         for (int p = 0; p < kPhases; ++p) {
@@ -66,15 +71,25 @@ hipError_t enqueue_batch(const BatchTable& t, const int* totals, int max_w, hipS
 
 }  // namespace edt
 
+// One way of laying out a batch: the table, its work totals and the widest
+// image taking the several-lanes-per-row row pass.
+struct Schedule {
+    int lane_w = edt::kLaneMaxW;   // widest image taking the one-lane-per-row pass
+    bool largest_first = false;   // images listed by decreasing width, then height
+    void* table = nullptr;        // device copy of the batch table
+    int totals[edt::kPhases] = {};
+    int max_w = 0;
+};
+
 struct edt_plan {
     int nimg = 0;
     int want_dist = 1;
     int any_feat = 0;
-    int max_w = 0;
-    int totals[edt::kPhases] = {};
     size_t ws_bytes = 0;
     int device = 0;
-    void* table = nullptr;  // device copy of the batch table
+    std::vector<edt::BatchImage> img;  // host rows, in the order given
+    std::vector<Schedule> sched;       // built so far
+    int chosen = 0;
     // captured launches for one set of buffers
     hipStream_t cap_stream = nullptr;
     hipGraph_t graph = nullptr;
@@ -94,8 +109,50 @@ void drop_graph(edt_plan* p) {
     for (auto& k : p->key) k = nullptr;
 }
 
-hipError_t enqueue(edt_plan* p, const edt::BatchTable& t, hipStream_t s) {
-    return edt::enqueue_batch(t, p->totals, p->max_w, s);
+// Build (table on the device) the schedule (lane_w, largest_first).
+edt_status make_schedule(edt_plan* p, int lane_w, bool largest_first, Schedule* out) {
+    const int n = p->nimg;
+    std::vector<edt::BatchImage> rows = p->img;
+    if (largest_first) {
+        std::stable_sort(rows.begin(), rows.end(), [](const edt::BatchImage& a,
+                                                      const edt::BatchImage& b) {
+            return a.W != b.W ? a.W > b.W : a.H > b.H;
+        });
+    }
+    std::vector<uint8_t> host(edt::table_bytes(n));
+    Schedule sc;
+    sc.lane_w = lane_w;
+    sc.largest_first = largest_first;
+    const edt_status st = edt::pack_table(rows.data(), n, lane_w, host.data(), sc.totals, &sc.max_w);
+    if (st != EDT_OK) return st;
+    if (hipMalloc(&sc.table, host.size()) != hipSuccess) return EDT_ERR_OUT_OF_MEMORY;
+    if (hipMemcpy(sc.table, host.data(), host.size(), hipMemcpyHostToDevice) != hipSuccess) {
+        (void)hipFree(sc.table);
+        return EDT_ERR_DEVICE;
+    }
+    *out = sc;
+    return EDT_OK;
+}
+
+hipError_t enqueue(edt_plan* p, const Schedule& sc, const uint8_t* mask_base, int32_t* dist_base,
+                   int32_t* feat_base, void* workspace, hipStream_t s) {
+    edt::BatchTable t = edt::table_view(static_cast<const uint8_t*>(sc.table), p->nimg);
+    t.mask_base = reinterpret_cast<uintptr_t>(mask_base);
+    t.dist_base = p->want_dist ? reinterpret_cast<uintptr_t>(dist_base) : 0;
+    t.feat_base = p->any_feat ? reinterpret_cast<uintptr_t>(feat_base) : 0;
+    t.ws_base = reinterpret_cast<uintptr_t>(workspace);
+    return edt::enqueue_batch(t, sc.totals, sc.max_w, s);
+}
+
+edt_status check_buffers(edt_plan* p, const uint8_t* mask_base, int32_t* dist_base,
+                         int32_t* feat_base, void* workspace, size_t workspace_bytes) {
+    if (!p || !mask_base || !workspace) return EDT_ERR_INVALID_ARG;
+    if (p->want_dist && !dist_base) return EDT_ERR_INVALID_ARG;
+    if (p->any_feat && !feat_base) return EDT_ERR_INVALID_ARG;
+    if (!p->want_dist && !p->any_feat) return EDT_ERR_INVALID_ARG;
+    if (workspace_bytes < p->ws_bytes || (reinterpret_cast<uintptr_t>(workspace) & 255) != 0)
+        return EDT_ERR_INVALID_ARG;
+    return EDT_OK;
 }
 
 }  // namespace
@@ -134,31 +191,33 @@ edt_status edt_batch_plan(const edt_image_desc* images, int32_t n, int32_t want_
         any_feat |= d.want_feature != 0;
         ws += edt::layout_for(d.H, d.W, false).total;
     }
-    std::vector<uint8_t> host(edt::table_bytes(n));
-    int totals[edt::kPhases], max_w = 0;
-    const edt_status pst = edt::pack_table(img.data(), n, host.data(), totals, &max_w);
-    if (pst != EDT_OK) return pst;
-
+    {  // every candidate schedule must fit int32 totals: check the default
+        std::vector<uint8_t> host(edt::table_bytes(n));
+        int totals[edt::kPhases], max_w = 0;
+        const edt_status pst =
+            edt::pack_table(img.data(), n, edt::kLaneMaxW, host.data(), totals, &max_w);
+        if (pst != EDT_OK) return pst;
+    }
     edt_plan* pl = new (std::nothrow) edt_plan;
     if (!pl) return EDT_ERR_OUT_OF_MEMORY;
     pl->nimg = n;
     pl->want_dist = want_dist != 0;
     pl->any_feat = any_feat;
-    pl->max_w = max_w;
-    for (int p = 0; p < edt::kPhases; ++p) pl->totals[p] = totals[p];
     pl->ws_bytes = ws;
+    pl->img = std::move(img);
     pl->use_graph = std::getenv("EDT_NO_GRAPH") == nullptr;
-    if (hipGetDevice(&pl->device) != hipSuccess || hipMalloc(&pl->table, host.size()) != hipSuccess) {
-        delete pl;
-        return EDT_ERR_OUT_OF_MEMORY;
-    }
-    bool ok = hipMemcpy(pl->table, host.data(), host.size(), hipMemcpyHostToDevice) == hipSuccess;
-    if (ok) ok = hipEventCreateWithFlags(&pl->done, hipEventDisableTiming) == hipSuccess;
-    if (ok && pl->use_graph)
-        ok = hipStreamCreateWithFlags(&pl->cap_stream, hipStreamNonBlocking) == hipSuccess;
-    if (!ok) {
+    Schedule sc;
+    edt_status st = hipGetDevice(&pl->device) == hipSuccess ? EDT_OK : EDT_ERR_DEVICE;
+    if (st == EDT_OK) st = make_schedule(pl, edt::kLaneMaxW, false, &sc);
+    if (st == EDT_OK) pl->sched.push_back(sc);
+    if (st == EDT_OK && hipEventCreateWithFlags(&pl->done, hipEventDisableTiming) != hipSuccess)
+        st = EDT_ERR_DEVICE;
+    if (st == EDT_OK && pl->use_graph &&
+        hipStreamCreateWithFlags(&pl->cap_stream, hipStreamNonBlocking) != hipSuccess)
+        st = EDT_ERR_DEVICE;
+    if (st != EDT_OK) {
         edt_plan_destroy(pl);
-        return EDT_ERR_DEVICE;
+        return st;
     }
     *plan = pl;
     *workspace_bytes = ws;
@@ -168,21 +227,15 @@ edt_status edt_batch_plan(const edt_image_desc* images, int32_t n, int32_t want_
 edt_status edt_batch_submit(edt_plan* p, const uint8_t* mask_base, int32_t* dist_base,
                             int32_t* feat_base, void* workspace, size_t workspace_bytes,
                             void* stream) {
-    if (!p || !mask_base || !workspace) return EDT_ERR_INVALID_ARG;
-    if (p->want_dist && !dist_base) return EDT_ERR_INVALID_ARG;
-    if (p->any_feat && !feat_base) return EDT_ERR_INVALID_ARG;
-    if (!p->want_dist && !p->any_feat) return EDT_ERR_INVALID_ARG;
-    if (workspace_bytes < p->ws_bytes || (reinterpret_cast<uintptr_t>(workspace) & 255) != 0)
-        return EDT_ERR_INVALID_ARG;
+    const edt_status cs = check_buffers(p, mask_base, dist_base, feat_base, workspace,
+                                        workspace_bytes);
+    if (cs != EDT_OK) return cs;
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-    edt::BatchTable t = edt::table_view(static_cast<const uint8_t*>(p->table), p->nimg);
-    t.mask_base = reinterpret_cast<uintptr_t>(mask_base);
-    t.dist_base = p->want_dist ? reinterpret_cast<uintptr_t>(dist_base) : 0;
-    t.feat_base = p->any_feat ? reinterpret_cast<uintptr_t>(feat_base) : 0;
-    t.ws_base = reinterpret_cast<uintptr_t>(workspace);
+    const Schedule& sc = p->sched[p->chosen];
     // Kernel timing needs the launches themselves, so it bypasses the graph.
     if (!p->use_graph || edt::prof_enabled()) {
-        if (enqueue(p, t, s) != hipSuccess) return EDT_ERR_DEVICE;
+        if (enqueue(p, sc, mask_base, dist_base, feat_base, workspace, s) != hipSuccess)
+            return EDT_ERR_DEVICE;
         return hipEventRecord(p->done, s) == hipSuccess ? EDT_OK : EDT_ERR_DEVICE;
     }
     const void* key[4] = {mask_base, p->want_dist ? dist_base : nullptr,
@@ -193,7 +246,8 @@ edt_status edt_batch_submit(edt_plan* p, const uint8_t* mask_base, int32_t* dist
         drop_graph(p);
         if (hipStreamBeginCapture(p->cap_stream, hipStreamCaptureModeThreadLocal) != hipSuccess)
             return EDT_ERR_DEVICE;
-        const hipError_t le = enqueue(p, t, p->cap_stream);
+        const hipError_t le = enqueue(p, sc, mask_base, dist_base, feat_base, workspace,
+                                      p->cap_stream);
         hipGraph_t g = nullptr;
         const hipError_t ce = hipStreamEndCapture(p->cap_stream, &g);
         if (le != hipSuccess || ce != hipSuccess || !g) {
@@ -211,6 +265,82 @@ edt_status edt_batch_submit(edt_plan* p, const uint8_t* mask_base, int32_t* dist
     return hipEventRecord(p->done, s) == hipSuccess ? EDT_OK : EDT_ERR_DEVICE;
 }
 
+edt_status edt_batch_autotune(edt_plan* p, const uint8_t* mask_base, int32_t* dist_base,
+                              int32_t* feat_base, void* workspace, size_t workspace_bytes,
+                              void* stream, edt_tune_report* report) {
+    const edt_status cs = check_buffers(p, mask_base, dist_base, feat_base, workspace,
+                                        workspace_bytes);
+    if (cs != EDT_OK) return cs;
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    int widest = 0;
+    for (const auto& b : p->img) widest = b.W > widest ? b.W : widest;
+    // candidate lane widths: none, then each width class up to kLaneMaxW that
+    // changes which images take the lane pass
+    std::vector<int> lane_ws = {0};
+    for (int w : {256, edt::kLaneMaxW}) {
+        const int eff = w < widest ? w : widest;
+        if (eff > lane_ws.back()) lane_ws.push_back(w);
+    }
+    struct Cand { int lane_w; bool largest; };
+    std::vector<Cand> cands;
+    for (int w : lane_ws)
+        for (bool lf : {false, true}) cands.push_back({w, lf});
+    if ((int)cands.size() > EDT_TUNE_MAX) cands.resize(EDT_TUNE_MAX);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+        if (e0) (void)hipEventDestroy(e0);
+        return EDT_ERR_DEVICE;
+    }
+    edt_status st = EDT_OK;
+    float best = 0.f;
+    int best_k = -1;
+    edt_tune_report rep;
+    memset(&rep, 0, sizeof(rep));
+    for (size_t c = 0; c < cands.size() && st == EDT_OK; ++c) {
+        int k = -1;
+        for (size_t q = 0; q < p->sched.size(); ++q)
+            if (p->sched[q].lane_w == cands[c].lane_w &&
+                p->sched[q].largest_first == cands[c].largest)
+                k = (int)q;
+        if (k < 0) {
+            Schedule sc;
+            st = make_schedule(p, cands[c].lane_w, cands[c].largest, &sc);
+            if (st != EDT_OK) break;
+            p->sched.push_back(sc);
+            k = (int)p->sched.size() - 1;
+        }
+        float t_min = 0.f;
+        for (int rep_i = 0; rep_i < 4 && st == EDT_OK; ++rep_i) {  // one warm-up, three timed
+            if (hipEventRecord(e0, s) != hipSuccess ||
+                enqueue(p, p->sched[k], mask_base, dist_base, feat_base, workspace, s) != hipSuccess ||
+                hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) {
+                st = EDT_ERR_DEVICE;
+                break;
+            }
+            float ms = 0.f;
+            if (hipEventElapsedTime(&ms, e0, e1) != hipSuccess) st = EDT_ERR_DEVICE;
+            if (rep_i > 0 && (rep_i == 1 || ms < t_min)) t_min = ms;
+        }
+        if (st != EDT_OK) break;
+        rep.lane_w[c] = cands[c].lane_w;
+        rep.largest_first[c] = cands[c].largest;
+        rep.ms[c] = t_min;
+        rep.tried = (int32_t)c + 1;
+        if (best_k < 0 || t_min < best) {
+            best = t_min;
+            best_k = k;
+            rep.chosen = (int32_t)c;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (st != EDT_OK) return st;
+    if (p->chosen != best_k) drop_graph(p);
+    p->chosen = best_k;
+    if (report) *report = rep;
+    return EDT_OK;
+}
+
 edt_status edt_plan_destroy(edt_plan* p) {
     if (!p) return EDT_ERR_INVALID_ARG;
     edt_status st = EDT_OK;
@@ -220,7 +350,8 @@ edt_status edt_plan_destroy(edt_plan* p) {
     }
     drop_graph(p);
     if (p->cap_stream) (void)hipStreamDestroy(p->cap_stream);
-    if (p->table && hipFree(p->table) != hipSuccess) st = EDT_ERR_DEVICE;
+    for (auto& sc : p->sched)
+        if (sc.table && hipFree(sc.table) != hipSuccess) st = EDT_ERR_DEVICE;
     delete p;
     return st;
 }

@@ -132,10 +132,10 @@ constexpr int kLaneRows = 64;
 constexpr int kLaneRing = 32;
 constexpr int kLaneMaxW = 1024;
 __host__ __device__ inline int items_lanes(int H) { return (H + kLaneRows - 1) / kLaneRows; }
-__host__ __device__ inline bool takes_lanes(int W) { return W <= kLaneMaxW; }
 
 // Phases of the transform, in launch order (a batch image's rows are work
-// items of kPhRows, or row groups of kPhLanes when takes_lanes(W)).
+// items of kPhRows, or row groups of kPhLanes when its width is at most the
+// batch's lane width, itself at most kLaneMaxW).
 enum Phase {
     kPhBits = 0,
     kPhCarry = 1,
@@ -217,13 +217,14 @@ __device__ inline int batch_image_of(const BatchTable& t, int p, int item) {
 
 // Batch tables (host side).  A table occupies table_bytes(n) bytes: the n
 // BatchImage rows, then per phase the n + 1 prefix entries, each part 256-byte
-// aligned.  pack_table writes it to host memory `dst` (images' H, W fields
-// set) and returns the work totals per phase and the widest image that the
-// row pass takes with several lanes per row;
-// EDT_ERR_TOO_LARGE if a total does not fit int32.  table_view points a
-// BatchTable at a copy of it in device memory.
+// aligned.  pack_table writes it to host memory `dst`: images no wider than
+// lane_w (<= kLaneMaxW) take the one-lane-per-row pass; it returns the work
+// totals per phase and the widest image that takes the pass with several
+// lanes per row; EDT_ERR_TOO_LARGE if a total does not fit int32.  table_view
+// points a BatchTable at a copy of it in device memory.
 size_t table_bytes(int n);
-int32_t pack_table(const BatchImage* img, int n, uint8_t* dst, int* totals, int* max_w);
+int32_t pack_table(const BatchImage* img, int n, int lane_w, uint8_t* dst, int* totals,
+                   int* max_w);
 BatchTable table_view(const uint8_t* dev_table, int n);
 // The whole transform of a batch, enqueued on stream.
 hipError_t enqueue_batch(const BatchTable& t, const int* totals, int max_w, hipStream_t stream);

@@ -157,7 +157,8 @@ bool launch(edt_server* s, Group& g) {
     }
     int totals[edt::kPhases], max_w = 0;
     uint8_t* host = s->staging[g.slot];
-    if (edt::pack_table(img.data(), n, host, totals, &max_w) != EDT_OK) return false;
+    if (edt::pack_table(img.data(), n, edt::kLaneMaxW, host, totals, &max_w) != EDT_OK)
+        return false;
     uint8_t* dev = s->tables + (size_t)g.slot * s->table_len;
     if (hipMemcpyAsync(dev, host, edt::table_bytes(n), hipMemcpyHostToDevice, st) != hipSuccess)
         return false;

@@ -132,3 +132,28 @@ def test_lane_rows_deep_pops_and_ties(edt):
     for (H, W) in [(1, 1), (1, 4096), (4096, 1), (3, 5), (64, 64)]:
         imgs.append(((rng.random((H, W)) < 0.3).astype(np.uint8), 0, True))
     _check_batch(edt, imgs, submits=2)
+
+
+def test_autotune_keeps_results_and_picks_the_fastest(edt):
+    import torch
+    dev = torch.device("cuda:0")
+    imgs = _images(12, 30, extra=[(70, 700, 0.3), (40, 1500, 0.05), (9, 200, 0.5)])
+    plan = edt.BatchPlan([(m.shape[0], m.shape[1], p, f) for m, p, f in imgs])
+    mask = plan.pack([m for m, _, _ in imgs], dev)
+    D, F = plan.outputs(dev)
+    ws = torch.empty(max(plan.workspace_bytes, 1), dtype=torch.uint8, device=dev)
+    cands, chosen = plan.autotune(mask, D, F, workspace=ws)
+    assert len(cands) >= 4 and 0 <= chosen < len(cands)
+    assert {c["lane_w"] for c in cands} >= {0, 256, 1024}
+    assert cands[chosen]["ms"] == min(c["ms"] for c in cands)
+    for rep in range(2):  # the tuned schedule, replayed
+        D.fill_(-9)
+        F.fill_(-9)
+        plan.submit(mask, D, F, workspace=ws)
+        torch.cuda.synchronize()
+        for q, (m, pol, wf) in enumerate(imgs):
+            Do, Fo = oracle.separable(m, pol)
+            assert np.array_equal(plan.image(D, q).cpu().numpy(), Do), (rep, q)
+            if wf:
+                assert np.array_equal(plan.image(F, q).cpu().numpy(), Fo), (rep, q)
+    plan.close()
