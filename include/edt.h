@@ -203,9 +203,10 @@ edt_status edt_plan_destroy(edt_plan *plan);
  * outputs) queue in arrival order; whenever launch slots are free, the
  * scheduler admits the longest prefix of the queue whose workspaces fit in
  * the memory budget and launches it at once, as one batch (the persistent
- * launches of edt_batch_submit) or, for a lone request or a row wider than
- * EDT_BATCH_MAX_W, as a single transform.  Requests arriving meanwhile join
- * the next launch.  Workspaces are carved from a caller-owned device arena.
+ * launches of edt_batch_submit) or, for a lone request, as a single
+ * transform; a request wider than 1024 columns is always launched alone (it
+ * fills the GPU by itself).  Requests arriving meanwhile join the next
+ * launch.  Workspaces are carved from a caller-owned device arena.
  * Results are bit-identical to edt_feature / edt_sq on the request alone. */
 typedef struct {
     size_t hbm_budget_bytes; /* arena bytes the server may hold at once for

@@ -50,12 +50,20 @@ struct Layout {
     size_t cols;       // int16  [cand_pitch(W)]  columns holding a site, increasing
     size_t meta;       // int32  [4]      {n = number of such columns, rc row pitch}
     size_t rc;         // int16  [H][cand_pitch(W)] nearest site row of each listed column
+    size_t segm;       // int16  [H][seg_count(W)]  envelope size of each row segment
     size_t slots;      // row slots for rows wider than kLdsMaxW (single images only)
     size_t total;
 };
 
-// Workspace layout of one image; with_slots adds the global row slots that
-// the single-image row pass uses for rows wider than kLdsMaxW.
+// Segments of the single-image row pass for dense rows: a row's candidate
+// list is cut into segments of kSegL (or a multiple of it) candidates, whose
+// envelopes are built one lane per (row, segment) and merged per row.
+constexpr int kSegL = 64;
+__host__ __device__ inline int seg_count(int W) { return (W + kSegL - 1) / kSegL; }
+__host__ __device__ inline bool has_segments(int W) { return W > kSparseMaxN && W <= kLdsMaxW; }
+
+// Workspace layout of one image; with_slots adds the global row slots and
+// segment sizes that the single-image row pass uses for wide rows.
 __host__ __device__ inline Layout layout_for(int H, int W, bool with_slots = true) {
     Layout L;
     L.nb = (H + kBand - 1) / kBand;
@@ -75,6 +83,8 @@ __host__ __device__ inline Layout layout_for(int H, int W, bool with_slots = tru
     off = align_up(off + 16, 256);
     L.rc = off;
     off = align_up(off + (size_t)H * cp * 2, 256);
+    L.segm = off;
+    if (with_slots && has_segments(W)) off = align_up(off + (size_t)H * seg_count(W) * 2, 256);
     L.slots = off;
     if (with_slots && W > kLdsMaxW) off = align_up(off + (size_t)kWideSlots * wide_slot_bytes(), 256);
     L.total = off;
@@ -263,6 +273,10 @@ hipError_t launch_column_pass_batch(const BatchTable& t, const int* totals, hipS
 hipError_t launch_row_pass_batch(const BatchTable& t, const int* totals, int max_w,
                                  hipStream_t stream);
 hipError_t launch_row_lanes_batch(const BatchTable& t, int total, hipStream_t stream);
+// Dense rows of one image (has_segments(W), more than kSparseMaxN candidates,
+// known only on the device): envelopes of row segments of L candidates, one
+// lane per (row, segment), sizes to `segm`.
+hipError_t launch_row_segscan(const Img& g, int L, int16_t* segm, hipStream_t stream);
 hipError_t launch_sqrt(const int32_t* D, float* out, int64_t n, hipStream_t stream);
 
 }  // namespace edt

@@ -114,13 +114,21 @@ struct Slots {
     __device__ __forceinline__ int16_t& s(int l) const { return st[at(l)]; }
 };
 
+// Slots stored in logical order (logical slot l at l).
+struct PlainSlots {
+    uint32_t* cand;
+    int16_t* st;
+    __device__ __forceinline__ uint32_t& c(int l) const { return cand[l]; }
+    __device__ __forceinline__ int16_t& s(int l) const { return st[l]; }
+};
+
 // Merge the envelope of chunk group R (first chunk g_r) into the group to its
 // left, L (first chunk g_l).  Per chunk c: survivors occupy logical slots
 // [lo, hi), nxt/prv link the non-empty chunks of a group, gf/gl hold the first
 // and last non-empty chunk of the group starting at c.  The first survivor of
 // a group always starts at pixel 0.
-template <int kM, int T, int S>
-__device__ void merge_groups(int g_l, int g_r, const Slots<T, S>& sl,
+template <int kM, typename SL>
+__device__ void merge_groups(int g_l, int g_r, const SL& sl,
                              int16_t* __restrict__ lo, int16_t* __restrict__ hi,
                              int16_t* __restrict__ nxt, int16_t* __restrict__ prv,
                              int16_t* __restrict__ gf, int16_t* __restrict__ gl, int i,
@@ -235,6 +243,53 @@ __device__ __forceinline__ void store4(int32_t* __restrict__ p, int j, int W, bo
     }
 }
 
+// Fill row i from its envelope (M survivors in column order: candidates in
+// cand, first owned pixels in st), four adjacent pixels per lane and store, so
+// that a wavefront writes 1 KiB of contiguous output per instruction.
+template <int kM, int T>
+__device__ __forceinline__ void fill_row(const Img& g, int i, const uint32_t* cand,
+                                         const int16_t* st, int M, bool vec) {
+    const int W = g.W;
+    const int t = threadIdx.x;
+    int32_t* drow = g.dist ? g.dist + (int64_t)i * g.opitch : nullptr;
+    int32_t* frow = g.feat ? g.feat + (int64_t)i * g.opitch : nullptr;
+    int e = 0;
+    for (int j = 4 * t; j < W; j += 4 * T) {
+        int d[4], f[4];
+        if (M == 0) {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                d[q] = INT32_MAX;
+                f[q] = -1;
+            }
+        } else {
+            // owner of pixel j: the last survivor starting at or before j,
+            // searched forward from this lane's previous owner
+            e = advance(st, e, M, j);
+            uint32_t C = cand[e];
+            int nst = e + 1 < M ? st[e + 1] : INT32_MAX;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int jj = j + q;
+                if (jj < W) {
+                    while (jj >= nst) {
+                        ++e;
+                        C = cand[e];
+                        nst = e + 1 < M ? st[e + 1] : INT32_MAX;
+                    }
+                    d[q] = dist_to<kM>(C, i, jj);
+                    f[q] = crow(C) * W + ccol(C);
+                } else {
+                    d[q] = 0;
+                    f[q] = 0;
+                }
+            }
+        }
+        if (drow) store4(drow, j, W, vec, d[0], d[1], d[2], d[3]);
+        if (frow) store4(frow, j, W, vec, f[0], f[1], f[2], f[3]);
+    }
+}
+
 // Row pass over the rows [i0, i1) (step di) of one image.  T lanes per row, S
 // candidate slots per lane.  A form takes an image only if the image's
 // device-side count n of candidate columns is in its range: the sparse form
@@ -346,7 +401,7 @@ __device__ void process_rows(const Img& g, int i0, int i1, int di,
         // 3. merge up the tree
         for (int w = 1; w < nchunks; w <<= 1) {
             if ((t & (2 * w - 1)) == 0 && t + w < nchunks)
-                merge_groups<kM, T, S>(t, t + w, sl, sh.lo, sh.hi, sh.nxt, sh.prv, sh.gf, sh.gl, i, W);
+                merge_groups<kM>(t, t + w, sl, sh.lo, sh.hi, sh.nxt, sh.prv, sh.gf, sh.gl, i, W);
             __syncthreads();
         }
         // 4. survivors to the front of the list, in column order (plain layout)
@@ -384,43 +439,7 @@ __device__ void process_rows(const Img& g, int i0, int i1, int di,
         }
         __syncthreads();
         // 5. fill, four adjacent pixels per lane and step
-        int32_t* drow = g.dist ? g.dist + (int64_t)i * g.opitch : nullptr;
-        int32_t* frow = g.feat ? g.feat + (int64_t)i * g.opitch : nullptr;
-        int e = 0;
-        for (int j = 4 * t; j < W; j += 4 * T) {
-            int d[4], f[4];
-            if (M == 0) {
-#pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    d[q] = INT32_MAX;
-                    f[q] = -1;
-                }
-            } else {
-                // owner of pixel j: the last survivor starting at or before j,
-                // searched forward from this lane's previous owner
-                e = advance(st, e, M, j);
-                uint32_t C = cand[e];
-                int nst = e + 1 < M ? st[e + 1] : INT32_MAX;
-#pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    const int jj = j + q;
-                    if (jj < W) {
-                        while (jj >= nst) {
-                            ++e;
-                            C = cand[e];
-                            nst = e + 1 < M ? st[e + 1] : INT32_MAX;
-                        }
-                        d[q] = dist_to<kM>(C, i, jj);
-                        f[q] = crow(C) * W + ccol(C);
-                    } else {
-                        d[q] = 0;
-                        f[q] = 0;
-                    }
-                }
-            }
-            if (drow) store4(drow, j, W, vec, d[0], d[1], d[2], d[3]);
-            if (frow) store4(frow, j, W, vec, f[0], f[1], f[2], f[3]);
-        }
+        fill_row<kM, T>(g, i, cand, st, M, vec);
         __syncthreads();  // the next row reuses the list and the chunk tables
     }
 }
@@ -431,6 +450,136 @@ __global__ __launch_bounds__(T) void k_row_single(Img g, uint8_t* __restrict__ s
     __shared__ RowLds<T, S, kSparse, kGlobal> sh;
     uint8_t* gslot = kGlobal ? slots + (size_t)blockIdx.x * wide_slot_bytes() : nullptr;
     process_rows<kM, T, S, kSparse, kGlobal>(g, blockIdx.x, g.H, gridDim.x, sh, gslot);
+}
+
+// Dense rows of one image after the segment scan: the envelope of segment c
+// (candidates [c L, (c + 1) L), built one lane per row and segment) holds
+// segm entries at slots c L + e of the row's output (packed candidate) and of
+// its candidate list (start).  Per row: copy them into LDS, merge the
+// segments up a binary tree (log2(n / L) levels), compact the survivors and
+// fill.  The form with T lanes takes widths in (8 T, 16 T].
+template <int T, int L>
+struct SegLds {
+    static constexpr int CAP = 16 * T;
+    static constexpr int G = CAP / L;
+    uint32_t cand[CAP];
+    int16_t st[CAP];
+    int16_t lo[G], hi[G], nxt[G], prv[G], gf[G], gl[G];
+    int pos[G];
+    int wsum[T / 64];
+};
+
+template <int T, int L>
+__global__ __launch_bounds__(T, T <= 512 ? 6 : 1) void k_row_segfill(Img g, const int16_t* __restrict__ segm) {
+    __shared__ SegLds<T, L> sh;
+    constexpr int CAP = SegLds<T, L>::CAP, NW = T / 64, PER = CAP / T;
+    static_assert(SegLds<T, L>::G <= T, "one lane per segment");
+    const Views v = views_of(g);
+    const int n = v.meta[0];
+    const int W = g.W;
+    if (n <= kSparseMaxN || W <= CAP / 2 || W > CAP) return;  // another form's image
+    const int pitch = v.meta[1];
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    const int nchunks = (n + L - 1) / L;
+    const int sstride = seg_count(W);
+    int32_t* base = g.dist ? g.dist : g.feat;
+    const bool vec = (!g.dist || reinterpret_cast<uintptr_t>(g.dist) % 16 == 0) &&
+                     (!g.feat || reinterpret_cast<uintptr_t>(g.feat) % 16 == 0) &&
+                     (g.opitch % 4 == 0);
+    const PlainSlots sl{sh.cand, sh.st};
+    for (int i = blockIdx.x; i < g.H; i += gridDim.x) {
+        const uint32_t* sc = reinterpret_cast<const uint32_t*>(base + (int64_t)i * g.opitch);
+        const int16_t* rr = v.rc + (int64_t)i * pitch;
+        if (t < nchunks) {
+            const int m = segm[(int64_t)i * sstride + t * (L / kSegL)];
+            sh.lo[t] = (int16_t)(t * L);
+            sh.hi[t] = (int16_t)(t * L + m);
+            sh.nxt[t] = -1;
+            sh.prv[t] = -1;
+            sh.gf[t] = (int16_t)(m > 0 ? t : -1);
+            sh.gl[t] = (int16_t)(m > 0 ? t : -1);
+        }
+        __syncthreads();
+        // four loads in flight per lane before their LDS writes wait
+#pragma unroll
+        for (int k0 = 0; k0 < PER; k0 += 4) {
+            uint32_t vc[4];
+            int16_t vs[4];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const int q = t + (k0 + k) * T;
+                if (q < n) {
+                    vc[k] = sc[q];
+                    vs[k] = rr[q];
+                }
+            }
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const int q = t + (k0 + k) * T;
+                if (q < n && q < sh.hi[q / L]) {
+                    sh.cand[q] = vc[k];
+                    sh.st[q] = vs[k];
+                }
+            }
+        }
+        __syncthreads();
+        for (int w = 1; w < nchunks; w <<= 1) {
+            if (t < nchunks && (t & (2 * w - 1)) == 0 && t + w < nchunks)
+                merge_groups<0>(t, t + w, sl, sh.lo, sh.hi, sh.nxt, sh.prv, sh.gf, sh.gl, i, W);
+            __syncthreads();
+        }
+        // survivors to the front, in column order
+        const int c = t < nchunks ? sh.hi[t] - sh.lo[t] : 0;
+        int incl = c;
+#pragma unroll
+        for (int d = 1; d < 64; d <<= 1) {
+            const int x = __shfl_up(incl, d, 64);
+            if (lane >= d) incl += x;
+        }
+        if (lane == 63) sh.wsum[wave] = incl;
+        __syncthreads();
+        int pos = incl - c, M = 0;
+#pragma unroll
+        for (int q = 0; q < NW; ++q) {
+            if (q < wave) pos += sh.wsum[q];
+            M += sh.wsum[q];
+        }
+        if (t < nchunks) sh.pos[t] = pos;
+        __syncthreads();
+        // in two rounds of slots: a survivor only moves down, so the first
+        // round's writes land below every slot the second round reads
+        constexpr int HALF = PER / 2;
+#pragma unroll
+        for (int r = 0; r < 2; ++r) {
+            uint32_t kc[HALF];
+            int16_t ks[HALF];
+            int kd[HALF];
+#pragma unroll
+            for (int k = 0; k < HALF; ++k) {
+                const int q = t + (r * HALF + k) * T;
+                kd[k] = -1;
+                if (q < n) {
+                    const int cq = q / L;
+                    if (q >= sh.lo[cq] && q < sh.hi[cq]) {
+                        kc[k] = sh.cand[q];
+                        ks[k] = sh.st[q];
+                        kd[k] = sh.pos[cq] + q - sh.lo[cq];
+                    }
+                }
+            }
+            __syncthreads();
+#pragma unroll
+            for (int k = 0; k < HALF; ++k) {
+                if (kd[k] >= 0) {
+                    sh.cand[kd[k]] = kc[k];
+                    sh.st[kd[k]] = ks[k];
+                }
+            }
+        }
+        __syncthreads();
+        fill_row<0, T>(g, i, sh.cand, sh.st, M, vec);
+        __syncthreads();  // the next row reuses the tables
+    }
 }
 
 // A batch: workgroup g takes the contiguous run of row items
@@ -490,6 +639,29 @@ hipError_t launch_batch(const BatchTable& tb, int total, hipStream_t stream) {
     return hipGetLastError();
 }
 
+template <int T, int L>
+hipError_t launch_segfill(const Img& g, const int16_t* segm, hipStream_t stream) {
+    static int per_cu = 0;
+    if (per_cu == 0) per_cu = blocks_per_cu(k_row_segfill<T, L>, T);
+    int grid = per_cu * device_cus();
+    if (grid > g.H) grid = g.H;
+    EDT_LAUNCH_AS("k_row_segfill", (k_row_segfill<T, L>), dim3(grid), dim3(T), 0, stream, g, segm);
+    return hipGetLastError();
+}
+
+// Dense rows of one image, squared Euclidean: segment scan, then merge + fill.
+hipError_t launch_rows_segments(const Img& g, hipStream_t stream) {
+    constexpr int L = kSegL;
+    int16_t* segm = reinterpret_cast<int16_t*>(g.ws + layout_for(g.H, g.W).segm);
+    hipError_t e = launch_row_segscan(g, L, segm, stream);
+    if (e != hipSuccess) return e;
+    const int W = g.W;
+    if (W <= 2048) return launch_segfill<128, L>(g, segm, stream);
+    if (W <= 4096) return launch_segfill<256, L>(g, segm, stream);
+    if (W <= 8192) return launch_segfill<512, L>(g, segm, stream);
+    return launch_segfill<1024, L>(g, segm, stream);
+}
+
 template <int kM>
 hipError_t launch_rows_metric(const Img& g, uint8_t* slots, hipStream_t stream) {
     // Both forms are enqueued; each returns at once unless the image's number
@@ -497,6 +669,7 @@ hipError_t launch_rows_metric(const Img& g, uint8_t* slots, hipStream_t stream) 
     hipError_t e = launch_single<kM, kSparseLanes, kRowS, true, false>(g, slots, stream);
     const int W = g.W;
     if (e != hipSuccess || W <= kSparseMaxN) return e;
+    if (kM == 0 && has_segments(W)) return launch_rows_segments(g, stream);
     if (W <= 2048) return launch_single<kM, 128, kRowS, false, false>(g, slots, stream);
     if (W <= 4096) return launch_single<kM, 256, kRowS, false, false>(g, slots, stream);
     if (W <= 8192) return launch_single<kM, 512, kRowS, false, false>(g, slots, stream);

@@ -334,7 +334,44 @@ __global__ __launch_bounds__(kLaneRows) void k_row_lanes_batch(BatchTable tb) {
     }
 }
 
+// Segment scan for dense rows of one image: block (row group x, segment y)
+// scans the segment's candidates [y L, min(n, (y + 1) L)) of 64 rows, one lane
+// per row, leaving each segment's envelope at ranks y L + e and its size in
+// segm[i][y].  Images with at most kSparseMaxN candidates are left to the
+// one-wavefront row pass.
+template <int L>
+__global__ __launch_bounds__(kLaneRows) void k_row_segscan(Img g, int16_t* __restrict__ segm) {
+    __shared__ LaneLds sh;
+    const Views v = views_of(g);
+    const int n = v.meta[0];
+    const int q0 = (int)blockIdx.y * L;
+    if (n <= kSparseMaxN || q0 >= n) return;
+    const int lane = threadIdx.x;
+    const int i = (int)blockIdx.x * kLaneRows + lane;
+    if (i >= g.H) return;
+    const int pitch = v.meta[1];
+    int32_t* base = g.dist ? g.dist : g.feat;
+    const bool vec = (!g.dist || reinterpret_cast<uintptr_t>(g.dist) % 16 == 0) &&
+                     (!g.feat || reinterpret_cast<uintptr_t>(g.feat) % 16 == 0) &&
+                     (g.opitch % 4 == 0);
+    uint32_t* sc = reinterpret_cast<uint32_t*>(base + (int64_t)i * g.opitch) + q0;
+    const int M = scan_row(i, min(L, n - q0), g.W, v.cols + q0, v.rc + (int64_t)i * pitch + q0, sc,
+                           vec, sh, lane);
+    segm[(int64_t)i * seg_count(g.W) + blockIdx.y * (L / kSegL)] = (int16_t)M;
+}
+
 }  // namespace
+
+hipError_t launch_row_segscan(const Img& g, int L, int16_t* segm, hipStream_t stream) {
+    const dim3 grid((unsigned)items_lanes(g.H), (unsigned)((g.W + L - 1) / L));
+    if (L == 64) {
+        EDT_LAUNCH_AS("k_row_segscan", k_row_segscan<64>, grid, dim3(kLaneRows), 0, stream, g, segm);
+    } else {
+        EDT_LAUNCH_AS("k_row_segscan", k_row_segscan<128>, grid, dim3(kLaneRows), 0, stream, g,
+                      segm);
+    }
+    return hipGetLastError();
+}
 
 hipError_t launch_row_lanes_batch(const BatchTable& tb, int total, hipStream_t stream) {
     if (total < 1) return hipSuccess;

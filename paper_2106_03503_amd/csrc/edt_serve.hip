@@ -10,8 +10,8 @@
 //      requests) becomes one group and is launched on the next stream, after
 //      the events that mark each request's mask as ready; a group of two or
 //      more runs as one batch over a table staged through pinned memory, a
-//      lone request (or one wider than the batch kernels take) as a single
-//      transform;
+//      lone request (or one wider than the one-lane-per-row pass takes,
+//      which is always launched alone) as a single transform;
 //   3. wait: spin (yielding) while work is in flight, sleep while idle.
 // Requests that arrive while groups run are picked up by the next launch, so
 // the batch size follows the load.  Admission is strictly in arrival order: a
@@ -106,7 +106,10 @@ void form_group(edt_server* s, Group& g) {
     const int cap = s->cfg.max_group;
     while (!s->queue.empty() && (int)g.reqs.size() < cap) {
         Req& r = s->queue.front();
-        const bool wide = r.r.W > EDT_BATCH_MAX_W;
+        // images whose rows the one-lane-per-row pass does not take have
+        // enough rows of work to fill the GPU alone, and the single-image row
+        // pass is the faster one for them: they are launched alone
+        const bool wide = r.r.W > edt::kLaneMaxW;
         if (wide && !g.reqs.empty()) break;
         size_t off = 0;
         if (!s->alloc.alloc(r.bytes, &off)) break;
