@@ -5,6 +5,7 @@ Workloads (--workload):
   points16k (default)  one step = one edt_feature call on a 16384 x 16384 image
                        with 30 random object points: the single-image size at
                        which the HBM roofline is measured;
+  points16k_sq         the same image through edt_sq (distances only);
   disks4k, disks4k_inside, bernoulli256
                        other single images (4096^2 disks outside / inside,
                        256^2 Bernoulli(0.01));
@@ -54,7 +55,7 @@ def algo_bytes(kernel: str, H: int, W: int, n: int, with_dist: bool = True) -> i
         return W + n * 2
     if kernel == "k_nearest_row":        # bits + carries of listed columns in, int16 rows out
         return nb * n * 12 + H * n * 2
-    if kernel.startswith("k_row_"):      # int16 rows in, int32 D and F out
+    if kernel.startswith("k_row_"):      # int16 rows in, int32 D and F (or D only) out
         return H * n * 2 + H * W * (8 if with_dist else 4)
     raise KeyError(kernel)
 
@@ -71,6 +72,10 @@ SINGLE = {
         H=16384, W=16384, polarity=0,
         desc="16384x16384 uint8 mask, 30 uniform random object points (Voronoi-style); "
              "int32 squared distance + int32 nearest-object index per pixel"),
+    "points16k_sq": dict(
+        H=16384, W=16384, polarity=0, call="edt_sq",
+        desc="16384x16384 uint8 mask, 30 uniform random object points; int32 squared "
+             "distance only (edt_sq)"),
     "disks4k": dict(
         H=4096, W=4096, polarity=0,
         desc="4096x4096 uint8 mask, 200 random filled disks (r 5-200) + Bernoulli(1e-4) "
@@ -94,7 +99,7 @@ SERVE_DESC = ("{n} requests arriving as a Poisson stream at {rate:g}/s: square u
 
 def make_mask(name):
     import workloads
-    if name == "points16k":
+    if name in ("points16k", "points16k_sq"):
         return workloads.points(16384, 16384, 30)
     if name.startswith("disks4k"):
         return workloads.disks(4096, 4096)
@@ -227,17 +232,25 @@ def run_single(args):
     ws = torch.empty(edt.workspace_bytes(H, W, True), dtype=torch.uint8, device=dev)
     stream = torch.cuda.current_stream()
 
+    sq_only = wl.get("call") == "edt_sq"
+
     def step():
-        edt.feature(mask, polarity=pol, out_dist=D, out_feat=F, workspace=ws, stream=stream)
+        if sq_only:
+            edt.sq(mask, polarity=pol, out=D, workspace=ws, stream=stream)
+        else:
+            edt.feature(mask, polarity=pol, out_dist=D, out_feat=F, workspace=ws, stream=stream)
 
     ms, kt = timed(step, args.steps, args.warmup)
     px = H * W
     out = base_line(args, px / (ms * 1e-3) / 1e9, ms,
                     {"workload": wl["desc"], "H": H, "W": W, "polarity": pol,
-                     "call": "edt_feature", "parallelism": "single GPU"})
-    out["roofline"] = roofline(kt, lambda k: algo_bytes(k, H, W, n), args.workload)
-    gbs = PATH_BYTES_PER_PX * px / (ms * 1e-3) / 1e9
-    out["path_hbm"] = {"bytes_per_px": PATH_BYTES_PER_PX, "achieved_GBs": round(gbs, 1),
+                     "call": "edt_sq" if sq_only else "edt_feature",
+                     "parallelism": "single GPU"})
+    out["roofline"] = roofline(kt, lambda k: algo_bytes(k, H, W, n, with_dist=not sq_only),
+                               args.workload)
+    path_b = PATH_BYTES_PER_PX - (4.0 if sq_only else 0.0)
+    gbs = path_b * px / (ms * 1e-3) / 1e9
+    out["path_hbm"] = {"bytes_per_px": path_b, "achieved_GBs": round(gbs, 1),
                        "frac": round(gbs / HBM_PEAK_GBS, 4)}
     out["kernels_ms_per_step"] = {k: round(v[1] / args.steps, 4) for k, v in sorted(kt.items())}
     if not args.no_cpu:
@@ -317,7 +330,11 @@ def run_serve(args):
     import torch
     import paper_2106_03503_amd as edt
     import workloads
-    reqs = workloads.serving_requests(args.requests, args.rate)
+    burst = args.rate <= 0  # every request at t = 0: the server's capacity
+    reqs = workloads.serving_requests(args.requests, 1000.0 if burst else args.rate)
+    if burst:
+        for r in reqs:
+            r["t"] = 0.0
     dev = torch.device("cuda:0")
     print(f"serve: drawing {len(reqs)} request masks", file=sys.stderr, flush=True)
     masks_np = [workloads.request_mask(r) for r in reqs]
@@ -366,14 +383,16 @@ def run_serve(args):
     wall, st = runs[med]
     value = st["gpix_per_s"]
     out = base_line(args, value, wall * 1e3,
-                    {"workload": SERVE_DESC.format(n=len(reqs), rate=args.rate),
+                    {"workload": SERVE_DESC.format(n=len(reqs), rate=args.rate) if not burst else
+                     SERVE_DESC.replace("arriving as a Poisson stream at {rate:g}/s",
+                                        "submitted at once").format(n=len(reqs)),
                      "requests": len(reqs), "pixels": int(px), "rate_per_s": args.rate,
                      "hbm_budget_GiB": args.budget_gib, "streams": args.streams,
                      "call": "edt_serve_submit / edt_serve_wait", "parallelism": "single GPU"})
     out["scaling"] = "strong"
-    offered = px / reqs[-1]["t"] / 1e9
+    offered = px / reqs[-1]["t"] / 1e9 if not burst else None
     gbs = bytes_path / (px / (value * 1e9)) / 1e9 if value > 0 else 0.0
-    out["serve"] = {"offered_gpix_per_s": round(offered, 3),
+    out["serve"] = {"offered_gpix_per_s": round(offered, 3) if offered else "burst",
                     "p50_ms": round(st["p50_ns"] / 1e6, 3), "p99_ms": round(st["p99_ns"] / 1e6, 3),
                     "mean_ms": round(st["mean_ns"] / 1e6, 3), "max_ms": round(st["max_ns"] / 1e6, 3),
                     "launches": st["launches"], "done": st["done"], "failed": st["failed"],
@@ -404,7 +423,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="points16k",
                     choices=sorted(list(SINGLE) + ["batch2048", "serve"]))
-    ap.add_argument("--rate", type=float, default=5000.0, help="serve: requests per second")
+    ap.add_argument("--rate", type=float, default=5000.0,
+                    help="serve: requests per second (0: all at once, the capacity)")
     ap.add_argument("--requests", type=int, default=400, help="serve: requests per replay")
     ap.add_argument("--budget-gib", type=float, default=16.0, help="serve: memory budget")
     ap.add_argument("--streams", type=int, default=4, help="serve: server streams")

@@ -334,41 +334,63 @@ __global__ __launch_bounds__(kLaneRows) void k_row_lanes_batch(BatchTable tb) {
     }
 }
 
-// Segment scan for dense rows of one image: block (row group x, segment y)
+// Segment scan for dense rows of one image: work item (row group, segment y)
 // scans the segment's candidates [y L, min(n, (y + 1) L)) of 64 rows, one lane
 // per row, leaving each segment's envelope at ranks y L + e and its size in
-// segm[i][y].  Images with at most kSparseMaxN candidates are left to the
-// one-wavefront row pass.
+// segm[i][y].  The grid is persistent over the items, whose count depends on
+// the device-side number n of listed columns; images with at most
+// kSparseMaxN of them are left to the one-wavefront row pass.
 template <int L>
 __global__ __launch_bounds__(kLaneRows) void k_row_segscan(Img g, int16_t* __restrict__ segm) {
     __shared__ LaneLds sh;
     const Views v = views_of(g);
     const int n = v.meta[0];
-    const int q0 = (int)blockIdx.y * L;
-    if (n <= kSparseMaxN || q0 >= n) return;
+    if (n <= kSparseMaxN) return;
+    const int nseg = (n + L - 1) / L;
+    const int total = items_lanes(g.H) * nseg;
     const int lane = threadIdx.x;
-    const int i = (int)blockIdx.x * kLaneRows + lane;
-    if (i >= g.H) return;
     const int pitch = v.meta[1];
     int32_t* base = g.dist ? g.dist : g.feat;
     const bool vec = (!g.dist || reinterpret_cast<uintptr_t>(g.dist) % 16 == 0) &&
                      (!g.feat || reinterpret_cast<uintptr_t>(g.feat) % 16 == 0) &&
                      (g.opitch % 4 == 0);
-    uint32_t* sc = reinterpret_cast<uint32_t*>(base + (int64_t)i * g.opitch) + q0;
-    const int M = scan_row(i, min(L, n - q0), g.W, v.cols + q0, v.rc + (int64_t)i * pitch + q0, sc,
-                           vec, sh, lane);
-    segm[(int64_t)i * seg_count(g.W) + blockIdx.y * (L / kSegL)] = (int16_t)M;
+    for (int item = blockIdx.x; item < total; item += gridDim.x) {
+        const int grp = item / nseg, y = item - grp * nseg;
+        const int q0 = y * L;
+        const int i = grp * kLaneRows + lane;
+        if (i < g.H) {
+            uint32_t* sc = reinterpret_cast<uint32_t*>(base + (int64_t)i * g.opitch) + q0;
+            const int M = scan_row(i, min(L, n - q0), g.W, v.cols + q0,
+                                   v.rc + (int64_t)i * pitch + q0, sc, vec, sh, lane);
+            segm[(int64_t)i * seg_count(g.W) + y * (L / kSegL)] = (int16_t)M;
+        }
+    }
+}
+
+template <typename K>
+int lane_blocks_per_cu(K kernel) {
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kernel, kLaneRows, 0) != hipSuccess ||
+        nb < 1)
+        nb = 1;
+    return nb;
 }
 
 }  // namespace
 
 hipError_t launch_row_segscan(const Img& g, int L, int16_t* segm, hipStream_t stream) {
-    const dim3 grid((unsigned)items_lanes(g.H), (unsigned)((g.W + L - 1) / L));
+    static int per_cu64 = 0, per_cu128 = 0;
+    const int most = items_lanes(g.H) * ((g.W + L - 1) / L);  // items if every column is listed
     if (L == 64) {
-        EDT_LAUNCH_AS("k_row_segscan", k_row_segscan<64>, grid, dim3(kLaneRows), 0, stream, g, segm);
+        if (per_cu64 == 0) per_cu64 = lane_blocks_per_cu(k_row_segscan<64>);
+        const int grid = min(most, per_cu64 * device_cus());
+        EDT_LAUNCH_AS("k_row_segscan", k_row_segscan<64>, dim3(grid), dim3(kLaneRows), 0, stream,
+                      g, segm);
     } else {
-        EDT_LAUNCH_AS("k_row_segscan", k_row_segscan<128>, grid, dim3(kLaneRows), 0, stream, g,
-                      segm);
+        if (per_cu128 == 0) per_cu128 = lane_blocks_per_cu(k_row_segscan<128>);
+        const int grid = min(most, per_cu128 * device_cus());
+        EDT_LAUNCH_AS("k_row_segscan", k_row_segscan<128>, dim3(grid), dim3(kLaneRows), 0, stream,
+                      g, segm);
     }
     return hipGetLastError();
 }
