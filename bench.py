@@ -55,6 +55,10 @@ def algo_bytes(kernel: str, H: int, W: int, n: int, with_dist: bool = True) -> i
         return W + n * 2
     if kernel == "k_nearest_row":        # bits + carries of listed columns in, int16 rows out
         return nb * n * 12 + H * n * 2
+    if kernel == "k_row_segscan":        # int16 rows in (segment envelopes stay on chip or spill)
+        return H * n * 2
+    if kernel == "k_row_segfill":        # int32 D and F (or D only) out
+        return H * W * (8 if with_dist else 4)
     if kernel.startswith("k_row_"):      # int16 rows in, int32 D and F (or D only) out
         return H * n * 2 + H * W * (8 if with_dist else 4)
     raise KeyError(kernel)
@@ -114,6 +118,7 @@ KERNEL_SOURCES = {
     "k_col_compact": ("edt_column.hip",), "k_nearest_row": ("edt_column.hip",),
     "k_row_sparse": ("edt_row.hip",), "k_row_dense": ("edt_row.hip",),
     "k_row_dense_global": ("edt_row.hip",), "k_row_lanes": ("edt_row_lanes.hip",),
+    "k_row_segscan": ("edt_row_lanes.hip",), "k_row_segfill": ("edt_row.hip",),
     "k_sqrt": ("edt_api.hip",),
 }
 
@@ -274,7 +279,11 @@ def run_batch(args):
     px = sum(m.size for m, _ in imgs)
 
     tune = None
-    if not args.no_autotune:
+    if args.schedule:
+        lw, lf = (int(x) for x in args.schedule.split(","))
+        plan.set_schedule(lw, bool(lf))
+        tune = {"fixed": {"lane_w": lw, "largest_first": bool(lf)}}
+    elif not args.no_autotune:
         cands, chosen = plan.autotune(mask, D, F, workspace=ws, stream=stream)
         tune = {"candidates": cands, "chosen": chosen}
 
@@ -433,6 +442,9 @@ def main():
                     help="batch2048: skip the per-image edt_feature leg")
     ap.add_argument("--no-autotune", action="store_true",
                     help="batch2048: keep the default schedule instead of autotuning it")
+    ap.add_argument("--schedule", default="",
+                    help="batch2048: use this schedule 'lane_w,largest_first' instead of "
+                         "autotuning (e.g. 1024,1)")
     ap.add_argument("--copy-calibration", action="store_true")
     args = ap.parse_args()
 

@@ -192,6 +192,13 @@ edt_status edt_batch_autotune(edt_plan *plan, const uint8_t *mask_base, int32_t 
                               int32_t *feat_base, void *workspace, size_t workspace_bytes,
                               void *stream, edt_tune_report *report);
 
+/* Use the schedule (lane_w = widest image given the one-lane-per-row row
+ * pass, 0..1024; largest_first != 0: images listed by decreasing size) for
+ * later submissions, e.g. one that edt_batch_autotune picked for batches of
+ * the same shapes.  Errors: EDT_ERR_INVALID_ARG, EDT_ERR_OUT_OF_MEMORY,
+ * EDT_ERR_DEVICE. */
+edt_status edt_batch_set_schedule(edt_plan *plan, int32_t lane_w, int32_t largest_first);
+
 /* Release a plan (its device tables and graphs).  Work already enqueued with
  * it must have completed. */
 edt_status edt_plan_destroy(edt_plan *plan);

@@ -209,6 +209,8 @@ def _bind_batch():
     P, i32, sz = ctypes.c_void_p, ctypes.c_int32, ctypes.c_size_t
     _lib.edt_batch_autotune.argtypes = [P, P, P, P, P, sz, P, P]
     _lib.edt_batch_autotune.restype = i32
+    _lib.edt_batch_set_schedule.argtypes = [P, i32, i32]
+    _lib.edt_batch_set_schedule.restype = i32
     _lib.edt_batch_plan.argtypes = [P, i32, i32, P, P]
     _lib.edt_batch_plan.restype = i32
     _lib.edt_batch_submit.argtypes = [P, P, P, P, P, sz, P]
@@ -305,6 +307,11 @@ class BatchPlan:
         cands = [{"lane_w": rep.lane_w[q], "largest_first": bool(rep.largest_first[q]),
                   "ms": round(float(rep.ms[q]), 4)} for q in range(rep.tried)]
         return cands, int(rep.chosen)
+
+    def set_schedule(self, lane_w: int, largest_first: bool):
+        """Use a known schedule (e.g. one autotune picked) for later submissions."""
+        _check(_lib.edt_batch_set_schedule(self._plan, int(lane_w), int(largest_first)),
+               "edt_batch_set_schedule")
 
     def close(self):
         if self._plan:

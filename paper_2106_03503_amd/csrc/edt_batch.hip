@@ -341,6 +341,24 @@ edt_status edt_batch_autotune(edt_plan* p, const uint8_t* mask_base, int32_t* di
     return EDT_OK;
 }
 
+edt_status edt_batch_set_schedule(edt_plan* p, int32_t lane_w, int32_t largest_first) {
+    if (!p || lane_w < 0 || lane_w > edt::kLaneMaxW) return EDT_ERR_INVALID_ARG;
+    const bool lf = largest_first != 0;
+    int k = -1;
+    for (size_t q = 0; q < p->sched.size(); ++q)
+        if (p->sched[q].lane_w == lane_w && p->sched[q].largest_first == lf) k = (int)q;
+    if (k < 0) {
+        Schedule sc;
+        const edt_status st = make_schedule(p, lane_w, lf, &sc);
+        if (st != EDT_OK) return st;
+        p->sched.push_back(sc);
+        k = (int)p->sched.size() - 1;
+    }
+    if (p->chosen != k) drop_graph(p);
+    p->chosen = k;
+    return EDT_OK;
+}
+
 edt_status edt_plan_destroy(edt_plan* p) {
     if (!p) return EDT_ERR_INVALID_ARG;
     edt_status st = EDT_OK;

@@ -148,8 +148,10 @@ __device__ __forceinline__ void fill_block(int b, const uint32_t* sc, const int1
 // piece, and a pop below the ring brings a block back, so the loop touches
 // memory in whole 64- and 32-byte pieces and waits for it only when it reads
 // the next 32 site rows or, rarely, brings a block back.
-__device__ int scan_row(const int i, const int n, const int W, const int16_t* __restrict__ cols,
-                        int16_t* rr, uint32_t* sc, const bool vec, LaneLds& sh, const int lane) {
+__device__ __forceinline__ int scan_row(const int i, const int n, const int W,
+                                        const int16_t* __restrict__ cols, int16_t* rr,
+                                        uint32_t* sc, const bool vec, LaneLds& sh,
+                                        const int lane) {
     int M = 0, base = 0;
     int colA = 0, rowA = 0, gA = 0, sA = 0;  // top entry (M - 1)
     uint32_t cB = 0;                         // entry below it (M - 2)

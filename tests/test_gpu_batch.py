@@ -156,4 +156,17 @@ def test_autotune_keeps_results_and_picks_the_fastest(edt):
             assert np.array_equal(plan.image(D, q).cpu().numpy(), Do), (rep, q)
             if wf:
                 assert np.array_equal(plan.image(F, q).cpu().numpy(), Fo), (rep, q)
+    for lane_w, lf in ((0, True), (256, False)):  # schedules set by hand
+        plan.set_schedule(lane_w, lf)
+        D.fill_(-9)
+        F.fill_(-9)
+        plan.submit(mask, D, F, workspace=ws)
+        torch.cuda.synchronize()
+        for q, (m, pol, wf) in enumerate(imgs):
+            Do, Fo = oracle.separable(m, pol)
+            assert np.array_equal(plan.image(D, q).cpu().numpy(), Do), (lane_w, q)
+            if wf:
+                assert np.array_equal(plan.image(F, q).cpu().numpy(), Fo), (lane_w, q)
+    with pytest.raises(edt.EDTError):
+        plan.set_schedule(2048, False)
     plan.close()
