@@ -139,7 +139,7 @@ __host__ __device__ inline int items_near(int H, int W) {
 // Row pass with one lane per row: rows per work item (one wavefront), stack
 // entries per lane kept in LDS, and the widest image of a batch that takes it.
 constexpr int kLaneRows = 64;
-constexpr int kLaneRing = 32;
+constexpr int kLaneRing = 16;
 constexpr int kLaneMaxW = 1024;
 __host__ __device__ inline int items_lanes(int H) { return (H + kLaneRows - 1) / kLaneRows; }
 

@@ -26,6 +26,8 @@ namespace edt {
 namespace {
 
 constexpr int R = kLaneRing;
+constexpr int RB = R / 2;  // stack entries per block moved between the ring and memory
+static_assert(RB % 8 == 0, "blocks are whole 16-byte pieces of starts");
 constexpr int kBlk = 32;  // candidates per load of site rows (64 bytes per lane)
 
 // LDS of one wavefront: the scan keeps the top R stack entries of every lane
@@ -88,38 +90,40 @@ __device__ __forceinline__ int last_at_or_before(const int16_t* st, int lo, int 
     return a;
 }
 
-// Move ring block [b, b + 16) of this lane to memory (ranks b..b+15 of
-// (sc, rr)); b is a multiple of 16.
+// Move ring block [b, b + RB) of this lane to memory (ranks b.. of (sc, rr));
+// b is a multiple of RB.
 __device__ __forceinline__ void spill_block(int b, uint32_t* sc, int16_t* rr, bool vec,
                                             LaneLds& sh, int lane) {
-    uint32_t c[16];
-    uint32_t sp[8];
+    uint32_t c[RB];
+    uint32_t sp[RB / 2];
 #pragma unroll
-    for (int k = 0; k < 16; ++k) c[k] = sh.ring.c[(b + k) % R][lane];
+    for (int k = 0; k < RB; ++k) c[k] = sh.ring.c[(b + k) % R][lane];
 #pragma unroll
-    for (int k = 0; k < 8; ++k)
+    for (int k = 0; k < RB / 2; ++k)
         sp[k] = (uint32_t)(uint16_t)sh.ring.s[(b + 2 * k) % R][lane] |
                 ((uint32_t)(uint16_t)sh.ring.s[(b + 2 * k + 1) % R][lane] << 16);
     if (vec) {
 #pragma unroll
-        for (int k = 0; k < 4; ++k)
+        for (int k = 0; k < RB / 4; ++k)
             *reinterpret_cast<int4*>(sc + b + 4 * k) =
                 make_int4((int)c[4 * k], (int)c[4 * k + 1], (int)c[4 * k + 2], (int)c[4 * k + 3]);
     } else {
 #pragma unroll
-        for (int k = 0; k < 16; ++k) sc[b + k] = c[k];
+        for (int k = 0; k < RB; ++k) sc[b + k] = c[k];
     }
-    *reinterpret_cast<int4*>(rr + b) = make_int4((int)sp[0], (int)sp[1], (int)sp[2], (int)sp[3]);
-    *reinterpret_cast<int4*>(rr + b + 8) = make_int4((int)sp[4], (int)sp[5], (int)sp[6], (int)sp[7]);
+#pragma unroll
+    for (int k = 0; k < RB / 8; ++k)
+        *reinterpret_cast<int4*>(rr + b + 8 * k) =
+            make_int4((int)sp[4 * k], (int)sp[4 * k + 1], (int)sp[4 * k + 2], (int)sp[4 * k + 3]);
 }
 
-// Bring block [b, b + 16) of this lane back from memory into the ring.
+// Bring block [b, b + RB) of this lane back from memory into the ring.
 __device__ __forceinline__ void fill_block(int b, const uint32_t* sc, const int16_t* rr, bool vec,
                                            LaneLds& sh, int lane) {
-    uint32_t c[16];
+    uint32_t c[RB];
     if (vec) {
 #pragma unroll
-        for (int k = 0; k < 4; ++k) {
+        for (int k = 0; k < RB / 4; ++k) {
             const int4 x = *reinterpret_cast<const int4*>(sc + b + 4 * k);
             c[4 * k] = (uint32_t)x.x;
             c[4 * k + 1] = (uint32_t)x.y;
@@ -128,14 +132,19 @@ __device__ __forceinline__ void fill_block(int b, const uint32_t* sc, const int1
         }
     } else {
 #pragma unroll
-        for (int k = 0; k < 16; ++k) c[k] = sc[b + k];
+        for (int k = 0; k < RB; ++k) c[k] = sc[b + k];
     }
-    const int4 s0 = *reinterpret_cast<const int4*>(rr + b);
-    const int4 s1 = *reinterpret_cast<const int4*>(rr + b + 8);
-    const uint32_t sp[8] = {(uint32_t)s0.x, (uint32_t)s0.y, (uint32_t)s0.z, (uint32_t)s0.w,
-                            (uint32_t)s1.x, (uint32_t)s1.y, (uint32_t)s1.z, (uint32_t)s1.w};
+    uint32_t sp[RB / 2];
 #pragma unroll
-    for (int k = 0; k < 16; ++k) {
+    for (int k = 0; k < RB / 8; ++k) {
+        const int4 x = *reinterpret_cast<const int4*>(rr + b + 8 * k);
+        sp[4 * k] = (uint32_t)x.x;
+        sp[4 * k + 1] = (uint32_t)x.y;
+        sp[4 * k + 2] = (uint32_t)x.z;
+        sp[4 * k + 3] = (uint32_t)x.w;
+    }
+#pragma unroll
+    for (int k = 0; k < RB; ++k) {
         sh.ring.c[(b + k) % R][lane] = c[k];
         sh.ring.s[(b + k) % R][lane] = (int16_t)(sp[k >> 1] >> (16 * (k & 1)));
     }
@@ -144,7 +153,7 @@ __device__ __forceinline__ void fill_block(int b, const uint32_t* sc, const int1
 // Scan of row i (this lane's row): builds the row's envelope as a stack and
 // leaves it in memory, entry e at rank e of (sc, rr); returns its size.  The
 // top two entries stay in registers and the ranks [base, M) in an LDS ring of
-// two 16-entry blocks; a full ring moves its older block to memory in one
+// two blocks of R/2 entries; a full ring moves its older block to memory in one
 // piece, and a pop below the ring brings a block back, so the loop touches
 // memory in whole 64- and 32-byte pieces and waits for it only when it reads
 // the next 32 site rows or, rarely, brings a block back.
@@ -194,7 +203,7 @@ __device__ __forceinline__ int scan_row(const int i, const int n, const int W,
                     if (M > 1) {
                         const int e = M - 2;
                         if (e < base) {  // below the ring: bring its block back
-                            base -= 16;
+                            base -= RB;
                             fill_block(base, sc, rr, vec, sh, lane);
                         }
                         cB = sh.ring.c[e % R][lane];
@@ -212,7 +221,7 @@ __device__ __forceinline__ int scan_row(const int i, const int n, const int W,
                 }
                 if (M - base == R) {  // ring full: its older block goes to memory
                     spill_block(base, sc, rr, vec, sh, lane);
-                    base += 16;
+                    base += RB;
                 }
                 sh.ring.c[M % R][lane] = ((uint32_t)col << 16) | (uint32_t)row;
                 sh.ring.s[M % R][lane] = (int16_t)s;
