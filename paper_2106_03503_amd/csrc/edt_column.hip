@@ -21,83 +21,84 @@
 namespace edt {
 namespace {
 
-constexpr int kColThreads = 256;
-
 // High bit of each byte of w set iff that byte is nonzero.
 __device__ __forceinline__ uint32_t nonzero_bytes(uint32_t w) {
     return (((w & 0x7F7F7F7Fu) + 0x7F7F7F7Fu) | w) & 0x80808080u;
 }
 
 // ---------------------------------------------------------------- bits
-// Work item (band b, column block bx) of 1024 columns: each of the four
-// wavefronts loads 16 rows of the band (16 columns per lane and row: one
-// 16-byte load when the mask allows, else four 4-byte or sixteen 1-byte
-// loads) and builds 16-bit partial column masks, joined through LDS into the
-// 64-bit band masks: bit r of bits[b][c] is set when pixel (b*kBand + r, c) is
-// a site.
-__device__ void bits_item(const Img& g, const Views& v, int item) {
-    __shared__ uint16_t s_part[4][16][65];
+// Work item (band b, block bx of kBitsCols columns) of one wavefront: lane l
+// owns the four columns bx*kBitsCols + 4l .. 4l + 3 and reads them as one
+// 4-byte word per row of the band.  Within a group of eight rows, the high
+// bit of each nonzero byte, shifted down by (7 - row in the group), lands on
+// bit (row in the group) of the same byte, so one word per group gathers
+// eight rows of the lane's four columns; byte x of the eight group words,
+// put side by side, is column x's 64-bit band mask: bit r of bits[b][c] is
+// set when pixel (b*kBand + r, c) is a site.
+//
+// Loads are whole aligned 4-byte words.  When the mask's base and row pitch
+// are multiples of 4 each lane reads one word per row; otherwise it reads the
+// one or two aligned words that hold its four bytes.  A word that holds a
+// pixel of the image may also hold bytes past column W - 1 (or before the
+// row's first byte); those bytes are read and ignored.  An aligned word never
+// straddles a page, so this reads no page the image does not touch.
+__device__ __forceinline__ uint32_t gather_byte(const uint32_t (&acc)[8], int g0, int x) {
+    uint32_t w = 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) w |= ((acc[g0 + k] >> (8 * x)) & 0xFFu) << (8 * k);
+    return w;
+}
+
+__device__ __forceinline__ void bits_item(const Img& g, const Views& v, int item, int lane) {
     const int nbx = (g.W + kBitsCols - 1) / kBitsCols;
     const int b = item / nbx, bx = item - b * nbx;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int cbase = bx * kBitsCols;
-    const int c = cbase + lane * 16;
-    const int rw0 = b * kBand + wave * 16;
-    const int rows = max(0, min(16, g.H - rw0));
-    const int ncols = max(0, min(16, g.W - c));
-    uint32_t part[16];
+    const int c = bx * kBitsCols + lane * 4;
+    const int row0 = b * kBand;
+    const int rows = min(kBand, g.H - row0);
+    const int ncols = min(4, g.W - c);
+    if (ncols <= 0) return;
+    const bool words = reinterpret_cast<uintptr_t>(g.mask) % 4 == 0 && g.mpitch % 4 == 0;
+    // rows past H (last band) read row H - 1 again; their bits are dropped
+    // below.  The row address is kept in scalar registers and the lane's
+    // column added as a 32-bit offset, so a row costs one load instruction.
+    const uint32_t cu = (uint32_t)c;
+    auto row_ptr = [&](int k) {
+        return global_ptr<const uint8_t>((uintptr_t)wave_uniform(reinterpret_cast<int64_t>(
+                   g.mask + (int64_t)(row0 + min(k, rows - 1)) * g.mpitch))) + cu;
+    };
+    uint32_t acc[8];
 #pragma unroll
-    for (int x = 0; x < 16; ++x) part[x] = 0u;
-    const uint8_t* p = g.mask + (int64_t)rw0 * g.mpitch + c;
-    const uint32_t flip = g.pol ? 0x80808080u : 0u;
-    const uintptr_t pa = reinterpret_cast<uintptr_t>(p);
-    if (ncols == 16 && rows == 16 && pa % 16 == 0 && g.mpitch % 16 == 0) {
-        uint4 q[16];
+    for (int k = 0; k < 8; ++k) acc[k] = 0u;
+    if (words) {
 #pragma unroll
-        for (int k = 0; k < 16; ++k) q[k] = *reinterpret_cast<const uint4*>(p + (int64_t)k * g.mpitch);
-#pragma unroll
-        for (int k = 0; k < 16; ++k) {
-            const uint32_t w4[4] = {q[k].x, q[k].y, q[k].z, q[k].w};
-#pragma unroll
-            for (int h = 0; h < 4; ++h) {
-                const uint32_t s = nonzero_bytes(w4[h]) ^ flip;
-#pragma unroll
-                for (int x = 0; x < 4; ++x) part[4 * h + x] |= ((s >> (8 * x + 7)) & 1u) << k;
-            }
+        for (int k = 0; k < kBand; ++k) {
+            const uint32_t w = *reinterpret_cast<const uint32_t*>(row_ptr(k));
+            acc[k >> 3] |= nonzero_bytes(w) >> (7 - (k & 7));
         }
-    } else if (ncols == 16 && pa % 4 == 0 && g.mpitch % 4 == 0) {
-        for (int k = 0; k < rows; ++k) {
-            const uint32_t* q = reinterpret_cast<const uint32_t*>(p + (int64_t)k * g.mpitch);
+    } else {
 #pragma unroll
-            for (int h = 0; h < 4; ++h) {
-                const uint32_t s = nonzero_bytes(q[h]) ^ flip;
-#pragma unroll
-                for (int x = 0; x < 4; ++x) part[4 * h + x] |= ((s >> (8 * x + 7)) & 1u) << k;
-            }
-        }
-    } else if (ncols > 0) {
-        const uint32_t pol = (uint32_t)g.pol;
-        for (int k = 0; k < rows; ++k) {
-            const uint8_t* q = p + (int64_t)k * g.mpitch;
-            for (int x = 0; x < ncols; ++x) part[x] |= ((uint32_t)(q[x] != 0) ^ pol) << k;
+        for (int k = 0; k < kBand; ++k) {
+            const uintptr_t a = reinterpret_cast<uintptr_t>(row_ptr(k));
+            const uint32_t* wp = global_ptr<const uint32_t>(a & ~(uintptr_t)3);
+            const int off = (int)(a & 3);
+            // the second word only when the four bytes reach into it (else the
+            // first again: its bytes then fall past the lane's columns)
+            const uint32_t lo = wp[0];
+            const uint32_t hi = wp[off + ncols > 4 ? 1 : 0];
+            const uint32_t w = (uint32_t)((((uint64_t)hi << 32) | lo) >> (8 * off));
+            acc[k >> 3] |= nonzero_bytes(w) >> (7 - (k & 7));
         }
     }
+    // rows past H hold no site; with polarity 1 the sites are the zero bytes
+    const uint64_t valid = rows == kBand ? ~0ull : (1ull << rows) - 1ull;
+    uint64_t* out = v.bits + (int64_t)b * g.W + c;
 #pragma unroll
-    for (int x = 0; x < 16; ++x) s_part[wave][x][lane] = (uint16_t)part[x];
-    __syncthreads();
-#pragma unroll
-    for (int y = 0; y < 4; ++y) {
-        const int cl = threadIdx.x * 4 + y;
-        const int cc = cbase + cl;
-        if (cc < g.W) {
-            const int ln = cl >> 4, x = cl & 15;
-            v.bits[(int64_t)b * g.W + cc] = (uint64_t)s_part[0][x][ln] |
-                                            ((uint64_t)s_part[1][x][ln] << 16) |
-                                            ((uint64_t)s_part[2][x][ln] << 32) |
-                                            ((uint64_t)s_part[3][x][ln] << 48);
+    for (int x = 0; x < 4; ++x) {
+        if (x < ncols) {
+            uint64_t m = ((uint64_t)gather_byte(acc, 4, x) << 32) | gather_byte(acc, 0, x);
+            out[x] = (g.pol ? ~m : m) & valid;
         }
     }
-    __syncthreads();  // s_part is reused by the next item of this workgroup
 }
 
 // --------------------------------------------------------------- carry
@@ -198,42 +199,68 @@ __device__ void compact_item(const Img& g, const Views& v) {
 }
 
 // ------------------------------------------------------------- nearest
-// Work item (band b, block qb of kNearCols listed columns): thread q handles
-// listed column q and writes rc[i][q] for the band's rows.  The last site at or
-// above the pixel (inside the band, else the carry from above) competes with
-// the first site at or below it (inside the band, else the carry from below);
-// the upper one wins at equal distance.  Items past the device-side count n
-// do nothing.
-__device__ void near_item(const Img& g, const Views& v, int item, int qblocks) {
-    const int n = v.meta[0];
-    const int pitch = v.meta[1];
+// Work item (band b, block qb of kNearCols listed columns) of one wavefront:
+// lane q handles listed column q and writes rc[i][q] for the band's rows.  A
+// bottom-up walk of the band's site bits gives, per row, the nearest site at
+// or below it (the carry from below past the band's last site); the top-down
+// walk that writes the rows keeps the nearest site at or above (the carry from
+// above before the band's first site).  Row i takes the upper site a rather
+// than the lower one d when i - a <= d - i -- the upper site wins at equal
+// distance -- i.e. when 2i <= a + d.  A missing side is a site kFar rows away,
+// farther than any real one.  Items past the device-side count n do nothing.
+constexpr int kFar = 1 << 20;
+
+__device__ __forceinline__ void near_item(const Img& g, const Views& v, int item, int qblocks,
+                                          int lane) {
+    const int n = wave_uniform(v.meta[0]);
+    const int pitch = wave_uniform(v.meta[1]);
     const int b = item / qblocks;
-    const int q = (item - b * qblocks) * kNearCols + threadIdx.x;
+    const int q = (item - b * qblocks) * kNearCols + lane;
     if (q >= n) return;
     const int c = v.cols[q];
     const int64_t bc = (int64_t)b * g.W + c;
     const uint64_t m = v.bits[bc];
-    const int u = v.up[bc];
-    const int d = v.down[bc];
+    const int up = v.up[bc];
+    const int down = v.down[bc];
     const int row0 = b * kBand;
     const int rows = min(kBand, g.H - row0);
-    int16_t* out = v.rc + (int64_t)row0 * pitch + q;
-    for (int r = 0; r < rows; ++r) {
-        const int i = row0 + r;
-        const uint64_t at_or_above = m & (r == 63 ? ~0ull : ((2ull << r) - 1));
-        const uint64_t at_or_below = m & (~0ull << r);
-        const int a = at_or_above ? row0 + 63 - __builtin_clzll(at_or_above) : u;
-        const int bl = at_or_below ? row0 + __builtin_ctzll(at_or_below) : d;
-        // the column holds a site, so at least one side exists
-        const int best = (a >= 0 && (bl == kNoBelow || i - a <= bl - i)) ? a : bl;
-        out[(int64_t)r * pitch] = (int16_t)best;
+    int a = up < 0 ? -kFar : up;
+    // quarters of 16 rows: the bottom-up walk of a quarter starts from the
+    // nearest site below it (the next set bit, else the carry from below)
+#pragma unroll
+    for (int h = 0; h < kBand / 16; ++h) {
+        if (16 * h < rows) {
+            const uint64_t after = h == 3 ? 0ull : m >> (16 * h + 16);
+            int d = after ? row0 + 16 * h + 16 + __builtin_ctzll(after)
+                          : (down == kNoBelow ? kFar : down);
+            const uint32_t mq = (uint32_t)(m >> (16 * h)) & 0xFFFFu;
+            int dn[16];
+#pragma unroll
+            for (int r = 15; r >= 0; --r) {
+                d = ((mq >> r) & 1u) ? row0 + 16 * h + r : d;
+                dn[r] = d;
+            }
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                const int i = row0 + 16 * h + r;
+                if (16 * h + r < rows) {
+                    a = ((mq >> r) & 1u) ? i : a;
+                    int16_t* row = v.rc + (int64_t)i * pitch;
+                    row[q] = (int16_t)(2 * i <= a + dn[r] ? a : dn[r]);
+                }
+            }
+        }
     }
 }
 
 // ------------------------------------------------------ single image
-__global__ __launch_bounds__(kColThreads) void k_bits(Img g) {
-    const Views v = views_of(g);
-    bits_item(g, v, blockIdx.x);
+__device__ __forceinline__ int wave_id() {
+    return __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+}
+
+__global__ __launch_bounds__(64 * kColWaves) void k_bits(Img g, int items) {
+    const int item = blockIdx.x * kColWaves + wave_id();
+    if (item < items) bits_item(g, views_of(g), item, threadIdx.x & 63);
 }
 __global__ __launch_bounds__(kCarryCols* kCarrySlices) void k_carry(Img g) {
     const Views v = views_of(g);
@@ -243,19 +270,22 @@ __global__ __launch_bounds__(1024) void k_compact(Img g) {
     const Views v = views_of(g);
     compact_item(g, v);
 }
-// persistent grid over the items (their useful number depends on n)
-__global__ __launch_bounds__(kNearCols) void k_near(Img g) {
+// persistent grid of wavefronts over the items (their useful number depends on n)
+__global__ __launch_bounds__(64 * kColWaves) void k_near(Img g) {
     const Views v = views_of(g);
     // items per band from the device-side count of listed columns
-    const int qblocks = (v.meta[0] + kNearCols - 1) / kNearCols;
+    const int qblocks = (wave_uniform(v.meta[0]) + kNearCols - 1) / kNearCols;
     const int items = ((g.H + kBand - 1) / kBand) * qblocks;
-    for (int item = blockIdx.x; item < items; item += gridDim.x) near_item(g, v, item, qblocks);
+    for (int item = blockIdx.x * kColWaves + wave_id(); item < items;
+         item += gridDim.x * kColWaves)
+        near_item(g, v, item, qblocks, threadIdx.x & 63);
 }
 
 // --------------------------------------------------------------- batch
-// Persistent grids over all work items of a phase in the batch; a workgroup
-// looks up the image of each item in the table (one binary search per item,
-// by thread 0, shared through LDS).
+// Persistent grids over all work items of a phase in the batch.  The band-bit
+// and nearest-row passes take one item per wavefront and find its image by a
+// binary search over the phase's prefix sums, uniform across the wavefront;
+// the carry pass takes one item per workgroup, looked up by thread 0.
 template <int kPh>
 __device__ __forceinline__ int batch_lookup(const BatchTable& t, int item) {
     __shared__ int s_img;
@@ -265,11 +295,12 @@ __device__ __forceinline__ int batch_lookup(const BatchTable& t, int item) {
     return s_img;
 }
 
-__global__ __launch_bounds__(kColThreads) void k_bits_batch(BatchTable t, int total) {
-    for (int item = blockIdx.x; item < total; item += gridDim.x) {
-        const int im = batch_lookup<kPhBits>(t, item);
+__global__ __launch_bounds__(64 * kColWaves) void k_bits_batch(BatchTable t, int total) {
+    for (int item = blockIdx.x * kColWaves + wave_id(); item < total;
+         item += gridDim.x * kColWaves) {
+        const int im = batch_image_of(t, kPhBits, item);
         const Img g = batch_img(t, im);
-        bits_item(g, views_of(g), item - t.prefix[kPhBits][im]);
+        bits_item(g, views_of(g), item - wave_uniform(t.prefix[kPhBits][im]), threadIdx.x & 63);
     }
 }
 __global__ __launch_bounds__(kCarryCols* kCarrySlices) void k_carry_batch(BatchTable t, int total) {
@@ -285,11 +316,14 @@ __global__ __launch_bounds__(1024) void k_compact_batch(BatchTable t, int total)
         compact_item(g, views_of(g));
     }
 }
-__global__ __launch_bounds__(kNearCols) void k_near_batch(BatchTable t, int total) {
-    for (int item = blockIdx.x; item < total; item += gridDim.x) {
-        const int im = batch_lookup<kPhNear>(t, item);
+__global__ __launch_bounds__(64 * kColWaves) void k_near_batch(BatchTable t, int total) {
+    for (int item = blockIdx.x * kColWaves + wave_id(); item < total;
+         item += gridDim.x * kColWaves) {
+        const int im = batch_image_of(t, kPhNear, item);
         const Img g = batch_img(t, im);
-        near_item(g, views_of(g), item - t.prefix[kPhNear][im], (g.W + kNearCols - 1) / kNearCols);
+        near_item(g, views_of(g), item - wave_uniform(t.prefix[kPhNear][im]),
+                  (g.W + kNearCols - 1) / kNearCols,
+                  threadIdx.x & 63);
     }
 }
 
@@ -310,29 +344,31 @@ int device_cus() {
 }
 
 hipError_t launch_column_pass(const Img& g, hipStream_t stream) {
-    EDT_LAUNCH_AS("k_band_bits", k_bits, dim3(items_bits(g.H, g.W)), dim3(kColThreads), 0,
-                  stream, g);
+    const int bits = items_bits(g.H, g.W);
+    EDT_LAUNCH_AS("k_band_bits", k_bits, dim3((bits + kColWaves - 1) / kColWaves),
+                  dim3(64 * kColWaves), 0, stream, g, bits);
     EDT_LAUNCH_AS("k_band_carry", k_carry, dim3(items_carry(g.H, g.W)),
                   dim3(kCarryCols * kCarrySlices), 0, stream, g);
     EDT_LAUNCH_AS("k_col_compact", k_compact, dim3(1), dim3(1024), 0, stream, g);
     // enough workgroups for a dense image, few enough that idle ones are cheap
-    const int items = items_near(g.H, g.W);
-    EDT_LAUNCH_AS("k_nearest_row", k_near, dim3(items < 2048 ? items : 2048), dim3(kNearCols), 0,
-                  stream, g);
+    const int near = (items_near(g.H, g.W) + kColWaves - 1) / kColWaves;
+    EDT_LAUNCH_AS("k_nearest_row", k_near, dim3(near < 2048 ? near : 2048), dim3(64 * kColWaves),
+                  0, stream, g);
     return hipGetLastError();
 }
 
 hipError_t launch_column_pass_batch(const BatchTable& t, const int* totals, hipStream_t stream) {
     const int cap = 16 * device_cus();
     auto grid = [&](int total) { return dim3((unsigned)(total < cap ? total : cap)); };
-    EDT_LAUNCH_AS("k_band_bits", k_bits_batch, grid(totals[kPhBits]), dim3(kColThreads), 0,
-                  stream, t, totals[kPhBits]);
+    auto wave_grid = [&](int total) { return grid((total + kColWaves - 1) / kColWaves); };
+    EDT_LAUNCH_AS("k_band_bits", k_bits_batch, wave_grid(totals[kPhBits]), dim3(64 * kColWaves),
+                  0, stream, t, totals[kPhBits]);
     EDT_LAUNCH_AS("k_band_carry", k_carry_batch, grid(totals[kPhCarry]),
                   dim3(kCarryCols * kCarrySlices), 0, stream, t, totals[kPhCarry]);
     EDT_LAUNCH_AS("k_col_compact", k_compact_batch, grid(totals[kPhCompact]), dim3(1024), 0,
                   stream, t, totals[kPhCompact]);
-    EDT_LAUNCH_AS("k_nearest_row", k_near_batch, grid(totals[kPhNear]), dim3(kNearCols), 0,
-                  stream, t, totals[kPhNear]);
+    EDT_LAUNCH_AS("k_nearest_row", k_near_batch, wave_grid(totals[kPhNear]),
+                  dim3(64 * kColWaves), 0, stream, t, totals[kPhNear]);
     return hipGetLastError();
 }
 

@@ -12,13 +12,16 @@ namespace edt {
 constexpr int kBand = 64;
 // "No site below" marker of the band carries (larger than any row index).
 constexpr int16_t kNoBelow = INT16_MAX;
-// Columns per workgroup of the band-bit pass (4 wavefronts x 64 lanes x 16).
-constexpr int kBitsCols = 1024;
+// Columns per work item (one wavefront, four per lane) of the band-bit pass.
+constexpr int kBitsCols = 256;
 // Band carries: columns per workgroup and band slices (one wavefront each).
 constexpr int kCarryCols = 64;
 constexpr int kCarrySlices = 16;
-// Listed columns per work item of the nearest-row pass.
-constexpr int kNearCols = 256;
+// Listed columns per work item (one wavefront) of the nearest-row pass.
+constexpr int kNearCols = 64;
+// Wavefronts per workgroup of the band-bit and nearest-row passes; each
+// wavefront takes work items of its own.
+constexpr int kColWaves = 4;
 
 // Row pass: candidate slots per lane.
 constexpr int kRowS = 16;
@@ -193,31 +196,52 @@ __device__ __forceinline__ T* global_ptr(uintptr_t a) {
     return (T*)(GT*)a;
 }
 
+// Values that every lane of the wavefront holds alike, moved to scalar
+// registers: the batch kernels take one image per wavefront at a time, and the
+// compiler cannot tell that what a wavefront reads from the batch table (in
+// memory that the kernel also writes) is the same in every lane.
+__device__ __forceinline__ int32_t wave_uniform(int32_t x) {
+    return __builtin_amdgcn_readfirstlane(x);
+}
+__device__ __forceinline__ int64_t wave_uniform(int64_t x) {
+    const uint64_t u = (uint64_t)x;
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)u);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(u >> 32));
+    return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+
+// Image im of the batch; im is the same in every lane of the wavefront.
 __device__ inline Img batch_img(const BatchTable& t, int im) {
     const BatchImage b = t.img[im];
+    const int64_t mask_off = wave_uniform((int64_t)b.mask_off);
+    const int64_t dist_off = wave_uniform((int64_t)b.dist_off);
+    const int64_t feat_off = wave_uniform((int64_t)b.feat_off);
+    const int64_t ws_off = wave_uniform((int64_t)b.ws_off);
+    const int outs = wave_uniform((int32_t)b.outs);
     Img g;
-    g.mask = global_ptr<const uint8_t>(t.mask_base + (uintptr_t)b.mask_off);
-    g.mpitch = b.mpitch;
-    g.dist = (b.outs & kOutDist) ? global_ptr<int32_t>(t.dist_base + 4 * (uintptr_t)b.dist_off)
-                                 : nullptr;
-    g.feat = (b.outs & kOutFeat) ? global_ptr<int32_t>(t.feat_base + 4 * (uintptr_t)b.feat_off)
-                                 : nullptr;
-    g.opitch = b.opitch;
-    g.ws = global_ptr<uint8_t>(t.ws_base + (uintptr_t)b.ws_off);
-    g.H = b.H;
-    g.W = b.W;
-    g.pol = b.pol;
+    g.mask = global_ptr<const uint8_t>(t.mask_base + (uintptr_t)mask_off);
+    g.mpitch = wave_uniform((int64_t)b.mpitch);
+    g.dist = (outs & kOutDist) ? global_ptr<int32_t>(t.dist_base + 4 * (uintptr_t)dist_off)
+                               : nullptr;
+    g.feat = (outs & kOutFeat) ? global_ptr<int32_t>(t.feat_base + 4 * (uintptr_t)feat_off)
+                               : nullptr;
+    g.opitch = wave_uniform((int64_t)b.opitch);
+    g.ws = global_ptr<uint8_t>(t.ws_base + (uintptr_t)ws_off);
+    g.H = wave_uniform((int32_t)b.H);
+    g.W = wave_uniform((int32_t)b.W);
+    g.pol = wave_uniform((int32_t)b.pol);
     g.metric = 0;
     return g;
 }
 
-// Image of work item `item` of phase p: the last image whose prefix is <= item.
+// Image of work item `item` of phase p: the last image whose prefix is <= item
+// (item is the same in every lane of the wavefront).
 __device__ inline int batch_image_of(const BatchTable& t, int p, int item) {
     const int32_t* pre = t.prefix[p];
     int a = 0, b = t.nimg - 1;
     while (a < b) {
         const int mid = (a + b + 1) >> 1;
-        if (pre[mid] <= item)
+        if (wave_uniform(pre[mid]) <= item)
             a = mid;
         else
             b = mid - 1;

@@ -81,6 +81,15 @@ def test_new_buffers_recapture(edt):
     _check_batch(edt, _images(3, 12), submits=3, fresh_buffers=True)
 
 
+def test_unpadded_rows_and_offsets(edt, monkeypatch):
+    # rows packed with no padding: mask rows and image offsets fall anywhere
+    # inside 4-byte words, output rows anywhere inside 16-byte lines
+    import paper_2106_03503_amd._lib as lib
+    monkeypatch.setattr(lib, "_round_up", lambda v, a: v)
+    imgs = _images(6, 30, extra=[(131, 1029, 0.02), (67, 301, 0.3), (3, 5, 0.5)])
+    _check_batch(edt, imgs, submits=2)
+
+
 def test_features_only_batch(edt):
     imgs = [(m, p, True) for m, p, _ in _images(4, 15)]
     _check_batch(edt, imgs, want_dist=False, submits=1)

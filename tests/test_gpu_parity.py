@@ -25,13 +25,13 @@ def edt():
     return edt
 
 
-def run(edt, m, pol, pitch_pad=0, out_pad=0):
+def run(edt, m, pol, pitch_pad=0, out_pad=0, col_off=0):
     import torch
     dev = torch.device("cuda:0")
     H, W = m.shape
-    big = torch.zeros((H, W + pitch_pad), dtype=torch.uint8, device=dev)
-    big[:, :W] = torch.from_numpy(m).to(dev)
-    mask = big[:, :W]
+    big = torch.zeros((H, col_off + W + pitch_pad), dtype=torch.uint8, device=dev)
+    big[:, col_off:col_off + W] = torch.from_numpy(m).to(dev)
+    mask = big[:, col_off:col_off + W]
     Dbuf = torch.full((H, W + out_pad), -7, dtype=torch.int32, device=dev)
     Fbuf = torch.full((H, W + out_pad), -7, dtype=torch.int32, device=dev)
     D, F = edt.feature(mask, polarity=pol, out_dist=Dbuf[:, :W], out_feat=Fbuf[:, :W])
@@ -180,3 +180,13 @@ def test_mask_load_paths(edt, W, pad):
     m = workloads.bernoulli(131, W, 0.01, seed=W + pad)
     check_exact(edt, m, 0, pitch_pad=pad)
     check_exact(edt, m, 1, pitch_pad=pad)
+
+
+@pytest.mark.parametrize("W,off,pad", [(1029, 1, 0), (300, 3, 1), (66, 2, 0), (5, 1, 0),
+                                       (1024, 4, 0)])
+def test_mask_base_off_word_boundary(edt, W, off, pad):
+    # the mask starts `off` bytes into its buffer: rows then begin inside a
+    # 4-byte word and the band-bit pass reads the words around each lane's bytes
+    m = workloads.bernoulli(131, W, 0.02, seed=3 * W + off)
+    check_exact(edt, m, 0, pitch_pad=pad, col_off=off)
+    check_exact(edt, m, 1, pitch_pad=pad, col_off=off)
