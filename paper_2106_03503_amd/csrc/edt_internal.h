@@ -186,6 +186,32 @@ struct BatchTable {
     uintptr_t ws_base;
 };
 
+// Integer products of pixel coordinates.  Every operand is a coordinate or
+// the difference or sum of two (below 2^16 in magnitude) and every product
+// stays below 2^31, so the 24-bit multiply gives it exactly -- at full issue
+// rate, where a 32-bit multiply issues at a quarter of it.
+__device__ __forceinline__ int mul_c(int a, int b) { return __mul24(a, b); }
+__device__ __forceinline__ int sqr_c(int x) { return __mul24(x, x); }
+
+// floor(num / den) + 1, clamped to [0, W], for 2 <= den < 2^16, num < 2^31
+// and W < 2^15: a float estimate of the quotient (relative error below 2^-21,
+// so within one of the floor wherever the result is below W), corrected with
+// the integer remainder.  It is the first pixel from which a parabola beats
+// its left neighbour when num/den is their intersection (Eq. eq_intersection,
+// with den = 2 (l - k)).
+__device__ __forceinline__ int first_after(int num, int den, int W) {
+    if (num < 0) return 0;
+    const float qf = (float)num * __builtin_amdgcn_rcpf((float)den);
+    int q = (int)qf;
+    if (q > W) return W;
+    const int r = num - mul_c(q, den);
+    if (r < 0)
+        --q;
+    else if (r >= den)
+        ++q;
+    return min(q + 1, W);
+}
+
 // A device address as a pointer into global memory.  Going through the
 // global address space lets the compiler emit global (not flat) loads and
 // stores for everything derived from it; a flat access also counts as an

@@ -49,7 +49,7 @@ __device__ __forceinline__ int crow(uint32_t c) { return (int)(c & 0xFFFFu); }
 template <int kM>
 __device__ __forceinline__ int dist_to(uint32_t C, int i, int j) {
     const int dr = i - crow(C), dc = j - ccol(C);
-    if (kM == 0) return dr * dr + dc * dc;
+    if (kM == 0) return sqr_c(dr) + sqr_c(dc);
     const int ar = dr < 0 ? -dr : dr, ac = dc < 0 ? -dc : dc;
     return kM == 1 ? ar + ac : max(ar, ac);
 }
@@ -75,12 +75,8 @@ __device__ __forceinline__ int first_win(uint32_t A, uint32_t B, int i, int W) {
     const int k = ccol(A), l = ccol(B), rk = crow(A), rl = crow(B);
     const int t = rl < rk ? 1 : 0;  // B wins ties
     if (kM == 0) {
-        const int dk = (i - rk) * (i - rk), dl = (i - rl) * (i - rl);
-        const int num = dl - dk + (l - k) * (l + k);
-        const int n2 = num - t;
-        if (n2 < 0) return 0;
-        const unsigned q = (unsigned)n2 / (2u * (unsigned)(l - k));
-        return q + 1u < (unsigned)W ? (int)q + 1 : W;
+        const int num = sqr_c(i - rl) - sqr_c(i - rk) + mul_c(l - k, l + k);
+        return first_after(num - t, 2 * (l - k), W);
     } else if (kM == 1) {
         const int fk = i > rk ? i - rk : rk - i, fl = i > rl ? i - rl : rl - i;
         const int a = fk + k, b = fl + l;
@@ -278,7 +274,7 @@ __device__ __forceinline__ void fill_row(const Img& g, int i, const uint32_t* ca
                         nst = e + 1 < M ? st[e + 1] : INT32_MAX;
                     }
                     d[q] = dist_to<kM>(C, i, jj);
-                    f[q] = crow(C) * W + ccol(C);
+                    f[q] = mul_c(crow(C), W) + ccol(C);
                 } else {
                     d[q] = 0;
                     f[q] = 0;

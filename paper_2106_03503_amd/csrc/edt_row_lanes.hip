@@ -27,6 +27,7 @@ namespace {
 
 constexpr int R = kLaneRing;
 constexpr int RB = R / 2;  // stack entries per block moved between the ring and memory
+static_assert((R & (R - 1)) == 0, "ring slots are taken modulo R with a mask");
 static_assert(RB % 8 == 0, "blocks are whole 16-byte pieces of starts");
 constexpr int kBlk = 32;  // candidates per load of site rows (64 bytes per lane)
 
@@ -42,25 +43,6 @@ union LaneLds {
         int16_t s[kLaneMaxW];
     } row;
 };
-
-__device__ __forceinline__ int sqr(int x) { return x * x; }
-
-// floor(num / den) + 1, clamped to [0, W], for den >= 2 and num < 2^31: a
-// float estimate of the quotient (relative error below 2^-21, so within one
-// of the floor wherever the result is below W), corrected with the integer
-// remainder.
-__device__ __forceinline__ int start_at(int num, int den, int W) {
-    if (num < 0) return 0;
-    const float qf = (float)num * __builtin_amdgcn_rcpf((float)den);
-    int q = (int)qf;
-    if (q > W) return W;
-    const int r = num - q * den;
-    if (r < 0)
-        --q;
-    else if (r >= den)
-        ++q;
-    return min(q + 1, W);
-}
 
 typedef int v4i __attribute__((ext_vector_type(4)));
 
@@ -97,11 +79,11 @@ __device__ __forceinline__ void spill_block(int b, uint32_t* sc, int16_t* rr, bo
     uint32_t c[RB];
     uint32_t sp[RB / 2];
 #pragma unroll
-    for (int k = 0; k < RB; ++k) c[k] = sh.ring.c[(b + k) % R][lane];
+    for (int k = 0; k < RB; ++k) c[k] = sh.ring.c[(b + k) & (R - 1)][lane];
 #pragma unroll
     for (int k = 0; k < RB / 2; ++k)
-        sp[k] = (uint32_t)(uint16_t)sh.ring.s[(b + 2 * k) % R][lane] |
-                ((uint32_t)(uint16_t)sh.ring.s[(b + 2 * k + 1) % R][lane] << 16);
+        sp[k] = (uint32_t)(uint16_t)sh.ring.s[(b + 2 * k) & (R - 1)][lane] |
+                ((uint32_t)(uint16_t)sh.ring.s[(b + 2 * k + 1) & (R - 1)][lane] << 16);
     if (vec) {
 #pragma unroll
         for (int k = 0; k < RB / 4; ++k)
@@ -145,8 +127,8 @@ __device__ __forceinline__ void fill_block(int b, const uint32_t* sc, const int1
     }
 #pragma unroll
     for (int k = 0; k < RB; ++k) {
-        sh.ring.c[(b + k) % R][lane] = c[k];
-        sh.ring.s[(b + k) % R][lane] = (int16_t)(sp[k >> 1] >> (16 * (k & 1)));
+        sh.ring.c[(b + k) & (R - 1)][lane] = c[k];
+        sh.ring.s[(b + k) & (R - 1)][lane] = (int16_t)(sp[k >> 1] >> (16 * (k & 1)));
     }
 }
 
@@ -163,7 +145,8 @@ __device__ __forceinline__ int scan_row(const int i, const int n, const int W,
                                         const int lane) {
     int M = 0, base = 0;
     int colA = 0, rowA = 0, gA = 0, sA = 0;  // top entry (M - 1)
-    uint32_t cB = 0;                         // entry below it (M - 2)
+    int dAs = 0, dAe = 0;  // the top's distances at its start sA and at pixel W - 1
+    uint32_t cB = 0;       // entry below it (M - 2)
     int sB = 0;
     for (int q0 = 0; q0 < n; q0 += kBlk) {
         static_assert(kBlk == 32, "four 16-byte loads of site rows per block");
@@ -188,17 +171,20 @@ __device__ __forceinline__ int scan_row(const int i, const int n, const int W,
                 if (u >= cnt) break;
                 const int row = (int)((rw[u8 >> 1] >> (16 * (u8 & 1))) & 0xFFFFu);
                 const int col = (int)((cw[u8 >> 1] >> (16 * (u8 & 1))) & 0xFFFFu);
-                const int gC = sqr(i - row);
+                const int gC = sqr_c(i - row);
+                const int dCe = gC + sqr_c(W - 1 - col);
                 // pop every parabola that the new one beats where it starts
                 while (M > 0) {
-                    const int dC = gC + sqr(sA - col), dA = gA + sqr(sA - colA);
-                    if (!(dC < dA || (dC == dA && row < rowA))) break;
+                    const int dC = gC + sqr_c(sA - col);
+                    if (!(dC < dAs || (dC == dAs && row < rowA))) break;
                     --M;
                     if (M > 0) {
                         colA = (int)(cB >> 16);
                         rowA = (int)(cB & 0xFFFFu);
-                        gA = sqr(i - rowA);
+                        gA = sqr_c(i - rowA);
                         sA = sB;
+                        dAs = gA + sqr_c(sA - colA);
+                        dAe = gA + sqr_c(W - 1 - colA);
                     }
                     if (M > 1) {
                         const int e = M - 2;
@@ -206,16 +192,15 @@ __device__ __forceinline__ int scan_row(const int i, const int n, const int W,
                             base -= RB;
                             fill_block(base, sc, rr, vec, sh, lane);
                         }
-                        cB = sh.ring.c[e % R][lane];
-                        sB = sh.ring.s[e % R][lane];
+                        cB = sh.ring.c[e & (R - 1)][lane];
+                        sB = sh.ring.s[e & (R - 1)][lane];
                     }
                 }
                 int s = 0;
                 if (M > 0) {
-                    const int dC = gC + sqr(W - 1 - col), dA = gA + sqr(W - 1 - colA);
-                    if (!(dC < dA || (dC == dA && row < rowA))) continue;  // never wins in the row
-                    s = start_at(gC - gA + (col - colA) * (col + colA) - (row < rowA ? 1 : 0),
-                                 2 * (col - colA), W);
+                    if (!(dCe < dAe || (dCe == dAe && row < rowA))) continue;  // never wins in the row
+                    s = first_after(gC - gA + mul_c(col - colA, col + colA) - (row < rowA ? 1 : 0),
+                                    2 * (col - colA), W);
                     cB = ((uint32_t)colA << 16) | (uint32_t)rowA;
                     sB = sA;
                 }
@@ -223,19 +208,21 @@ __device__ __forceinline__ int scan_row(const int i, const int n, const int W,
                     spill_block(base, sc, rr, vec, sh, lane);
                     base += RB;
                 }
-                sh.ring.c[M % R][lane] = ((uint32_t)col << 16) | (uint32_t)row;
-                sh.ring.s[M % R][lane] = (int16_t)s;
+                sh.ring.c[M & (R - 1)][lane] = ((uint32_t)col << 16) | (uint32_t)row;
+                sh.ring.s[M & (R - 1)][lane] = (int16_t)s;
                 colA = col;
                 rowA = row;
                 gA = gC;
                 sA = s;
+                dAs = gC + sqr_c(s - col);
+                dAe = dCe;
                 ++M;
             }
         }
     }
     for (int e = base; e < M; ++e) {  // the rest of the stack to memory
-        sc[e] = sh.ring.c[e % R][lane];
-        rr[e] = sh.ring.s[e % R][lane];
+        sc[e] = sh.ring.c[e & (R - 1)][lane];
+        rr[e] = sh.ring.s[e & (R - 1)][lane];
     }
     return M;
 }
@@ -333,8 +320,8 @@ __global__ __launch_bounds__(kLaneRows) void k_row_lanes_batch(BatchTable tb) {
                             nst = e + 1 < M ? sh.row.s[e + 1] : INT32_MAX;
                         }
                         const int col = (int)(c >> 16), row = (int)(c & 0xFFFFu);
-                        d[q] = sqr(i - row) + sqr(jj - col);
-                        f[q] = row * W + col;
+                        d[q] = sqr_c(i - row) + sqr_c(jj - col);
+                        f[q] = mul_c(row, W) + col;
                     }
                 }
             }
