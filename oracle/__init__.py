@@ -70,6 +70,8 @@ def bind(path: str):
     lib.oracle_sqrt_f32.restype = None
     lib.oracle_brute_metric.argtypes = [P, i32, i32, i64, i32, i32, P, P]
     lib.oracle_brute_metric.restype = i64
+    lib.oracle_chamfer_scans.argtypes = [P, i32, i32, i64, i32, i32, P]
+    lib.oracle_chamfer_scans.restype = None
     lib.oracle_cityblock_scans.argtypes = [P, i32, i32, i64, i32, i32, P]
     lib.oracle_cityblock_scans.restype = None
     return lib
@@ -194,7 +196,8 @@ def sqrt_f32(D):
 
 
 def brute_metric(mask, metric: int, polarity: int = 0):
-    """O1 for metric 1 (city-block) or 2 (chessboard): (D, F), D unsquared."""
+    """O1 for metric 1 (city-block), 2 (chessboard) or 3 (chamfer 4-3, scaled
+    by 3): (D, F), D unsquared."""
     m = _mask(mask)
     H, W = m.shape
     D = np.empty((H, W), np.int32)
@@ -210,4 +213,14 @@ def cityblock_scans(mask, polarity: int = 0, stages: int = 4):
     H, W = m.shape
     D = np.empty((H, W), np.int32)
     _load().oracle_cityblock_scans(_ptr(m), H, W, W, polarity, stages, _ptr(D))
+    return D
+
+
+def chamfer_scans(mask, polarity: int = 0, passes: int = 2):
+    """Chamfer 4-3 distances (scaled by 3) by the two raster scans of Section
+    2.2 (passes=1: only the forward scan)."""
+    m = _mask(mask)
+    H, W = m.shape
+    D = np.empty((H, W), np.int32)
+    _load().oracle_chamfer_scans(_ptr(m), H, W, W, polarity, passes, _ptr(D))
     return D

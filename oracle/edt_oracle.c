@@ -38,10 +38,13 @@
  *   oracle_sqrt_f32      d = sqrt(D) drawn after all squared distances are known
  *                        (Section 3.1), in fp64 then rounded to fp32.
  *   oracle_brute_metric  O1 for the city-block (e=1) and chessboard (e=inf)
- *                        members of the Minkowski family (Eq. eq_Minkowski).
+ *                        members of the Minkowski family (Eq. eq_Minkowski),
+ *                        and for the chamfer 4-3 metric (Section 1.3.2).
  *   oracle_cityblock_scans  the city-block transform by the four propagation
  *                        scans of Section 2.1 (columns down and up, then rows
  *                        forward and backward, one comparison per pixel each).
+ *   oracle_chamfer_scans the chamfer 4-3 transform by the two raster scans of
+ *                        Section 2.2 (four comparisons per pixel and scan).
  *
  * Integer arithmetic is done in int64 throughout; nothing here is tuned.
  */
@@ -480,9 +483,13 @@ void oracle_sqrt_f32(const int32_t *D, int64_t n, float *out)
 /* ------------------------------------------------- other Minkowski metrics */
 
 /* O1 for the other exact members of the Minkowski family (Eq. eq_Minkowski):
- * metric 1 = city-block (e = 1), metric 2 = chessboard (e = infinity).  D is the
- * distance itself (not squared); F the smallest linear index among the nearest
- * sites.  Returns the number of sites. */
+ * metric 1 = city-block (e = 1), metric 2 = chessboard (e = infinity); and
+ * metric 3 = the chamfer 4-3 distance of Section 1.3.2, the length of the
+ * shortest 8-connected path when a horizontal or vertical step costs 3 and a
+ * diagonal step 4 (Eq. eq_rel scaled by 3): min(di, dj) diagonal steps and
+ * max - min straight ones.  D is the distance itself (not squared); F the
+ * smallest linear index among the nearest sites.  Returns the number of
+ * sites. */
 int64_t oracle_brute_metric(const uint8_t *mask, int32_t H, int32_t W,
                             int64_t pitch, int32_t polarity, int32_t metric,
                             int32_t *D, int32_t *F)
@@ -495,7 +502,10 @@ int64_t oracle_brute_metric(const uint8_t *mask, int32_t H, int32_t W,
             for (int64_t q = 0; q < n; ++q) {
                 int64_t di = llabs((int64_t)i - s[q].r);
                 int64_t dj = llabs((int64_t)j - s[q].c);
-                int64_t d = (metric == 1) ? di + dj : (di > dj ? di : dj);
+                int64_t lo = di < dj ? di : dj, hi = di < dj ? dj : di;
+                int64_t d = (metric == 1) ? di + dj
+                          : (metric == 2) ? hi
+                                          : 4 * lo + 3 * (hi - lo);
                 if (best < 0 || d < best) {
                     best = d;
                     bestf = (int64_t)s[q].r * W + s[q].c;
@@ -545,6 +555,51 @@ void oracle_cityblock_scans(const uint8_t *mask, int32_t H, int32_t W, int64_t p
                 if (row[j] > row[j + 1] + 1) row[j] = row[j + 1] + 1;
         }
     }
+    for (int64_t q = 0; q < (int64_t)H * W; ++q)
+        D[q] = d[q] >= big ? ORACLE_INF_SQ : (int32_t)d[q];
+    free(d);
+}
+
+/* Chamfer 4-3 distance transform by the two raster scans of Section 2.2, all
+ * distances scaled by 3 (Eq. eq_rel: steps of 3 horizontally and vertically,
+ * 4 diagonally).  Sites start at 0 and every other pixel above any reachable
+ * distance.  The forward scan takes the rows top-down and each row left to
+ * right, and lowers d(i,j) to d(i,j-1)+3, d(i-1,j)+3, d(i-1,j-1)+4 and
+ * d(i-1,j+1)+4 in turn where that is smaller; the backward scan takes the rows
+ * bottom-up and each row right to left with d(i,j+1)+3, d(i+1,j)+3,
+ * d(i+1,j-1)+4 and d(i+1,j+1)+4.  passes = 1 stops after the forward scan
+ * (Figure fig_chamfer43DT(a)), passes = 2 gives the transform (Figure
+ * fig_chamfer43DT(b)).  Pixels no site reaches come out as INT32_MAX. */
+void oracle_chamfer_scans(const uint8_t *mask, int32_t H, int32_t W, int64_t pitch,
+                          int32_t polarity, int32_t passes, int32_t *D)
+{
+    const int64_t big = 4 * ((int64_t)H + W); /* above 4 (H-1) + 3 (W-1) and the mirror */
+    int64_t *d = (int64_t *)malloc(sizeof(int64_t) * (size_t)H * (size_t)W);
+#define AT(i, j) d[(int64_t)(i) * W + (j)]
+#define LOWER(i, j, v) do { if (AT(i, j) > (v)) AT(i, j) = (v); } while (0)
+    for (int32_t i = 0; i < H; ++i)
+        for (int32_t j = 0; j < W; ++j)
+            AT(i, j) = is_site(mask[(int64_t)i * pitch + j], polarity) ? 0 : big;
+    for (int32_t i = 0; i < H; ++i) { /* forward: top-left to bottom-right */
+        for (int32_t j = 0; j < W; ++j) {
+            if (j > 0) LOWER(i, j, AT(i, j - 1) + 3);
+            if (i > 0) LOWER(i, j, AT(i - 1, j) + 3);
+            if (i > 0 && j > 0) LOWER(i, j, AT(i - 1, j - 1) + 4);
+            if (i > 0 && j + 1 < W) LOWER(i, j, AT(i - 1, j + 1) + 4);
+        }
+    }
+    if (passes >= 2) {
+        for (int32_t i = H - 1; i >= 0; --i) { /* backward: bottom-right to top-left */
+            for (int32_t j = W - 1; j >= 0; --j) {
+                if (j + 1 < W) LOWER(i, j, AT(i, j + 1) + 3);
+                if (i + 1 < H) LOWER(i, j, AT(i + 1, j) + 3);
+                if (i + 1 < H && j > 0) LOWER(i, j, AT(i + 1, j - 1) + 4);
+                if (i + 1 < H && j + 1 < W) LOWER(i, j, AT(i + 1, j + 1) + 4);
+            }
+        }
+    }
+#undef LOWER
+#undef AT
     for (int64_t q = 0; q < (int64_t)H * W; ++q)
         D[q] = d[q] >= big ? ORACLE_INF_SQ : (int32_t)d[q];
     free(d);

@@ -92,3 +92,72 @@ def test_metric_closed_forms_and_invariants(metric):
     D1, _ = oracle.brute_metric(m, 1)
     D2, _ = oracle.brute_metric(m, 2)
     assert (D2 <= D1).all() and (D1 <= 2 * D2).all()
+
+
+# ---------------------------------------------------------------- chamfer 4-3
+
+def _float_table(name):
+    import os
+    from tests.golden_io import GOLDEN
+    rows = []
+    with open(os.path.join(GOLDEN, name)) as f:
+        for line in f:
+            line = line.split("#", 1)[0].split()
+            if line:
+                rows.append([float(v) for v in line])
+    return np.array(rows)
+
+
+@pytest.mark.parametrize("polarity", [0, 1])
+def test_chamfer_definition_matches_figure(polarity):
+    # Figure fig_chamfer(b) prints (d/3)^2 rounded to one decimal
+    D, F = oracle.brute_metric(_centre_site(polarity), 3, polarity)
+    assert np.array_equal(np.round(10 * (D / 3.0) ** 2) / 10, _float_table("fig_chamfer_b.txt"))
+    assert (F == 4 * 10 + 4).all()
+
+
+def test_chamfer_forward_scan_matches_figure_but_the_erratum():
+    D = oracle.chamfer_scans(workloads.paper_example(), passes=1).astype(np.int64)
+    D[D == INF_SQ] = INF
+    want = table("fig_chamfer43dt_a.txt")
+    ok = np.ones(want.shape, bool)
+    ok[8, 1] = False  # printed 14; the upper neighbour's 9 + 3 is smaller
+    assert np.array_equal(D[ok], want[ok])
+    assert D[8, 1] == 12 and D[7, 1] == 9
+
+
+def test_chamfer_final_matches_figure():
+    m = workloads.paper_example()
+    want = table("fig_chamfer43dt_b.txt")
+    assert np.array_equal(oracle.chamfer_scans(m), want)
+    assert np.array_equal(oracle.brute_metric(m, 3)[0], want)
+
+
+@pytest.mark.parametrize("seed", range(12))
+def test_chamfer_scans_equal_definition(seed):
+    # the two raster scans reach, at every pixel, the shortest 3/4-step path
+    # to the nearest site, which the definition takes as min(di,dj) diagonal
+    # and |di-dj| straight steps
+    rng = np.random.default_rng(100 + seed)
+    H, W = int(rng.integers(1, 40)), int(rng.integers(1, 40))
+    m = (rng.random((H, W)) < rng.choice([0.0, 0.005, 0.05, 0.3, 1.0])).astype(np.uint8)
+    for pol in (0, 1):
+        assert np.array_equal(oracle.chamfer_scans(m, pol), oracle.brute_metric(m, 3, pol)[0])
+
+
+def test_chamfer_bounds_against_euclidean():
+    # d/3 lies within [4/(3 sqrt 2), sqrt(10)/3] of the Euclidean distance
+    # (offsets along a diagonal, and with |di| = 3 |dj|), and both ends are met
+    rng = np.random.default_rng(7)
+    m = (rng.random((60, 70)) < 0.003).astype(np.uint8)
+    C, _ = oracle.brute_metric(m, 3)
+    E, _ = oracle.brute(m)
+    e = np.sqrt(E.astype(np.float64))
+    c = C / 3.0
+    nz = E > 0
+    lo, hi = 4 / (3 * np.sqrt(2)), np.sqrt(10) / 3
+    assert (c[nz] >= lo * e[nz] - 1e-12).all() and (c[nz] <= hi * e[nz] + 1e-12).all()
+    one = np.zeros((31, 31), np.uint8)
+    one[15, 15] = 1
+    C1, _ = oracle.brute_metric(one, 3)
+    assert C1[15 + 9, 15 + 9] == 36 and C1[15 + 9, 15 + 3] == 30  # diagonal; di = 3 dj

@@ -51,8 +51,18 @@ MUTANTS = [
     ("city-block scans skip the backward row scan",
      "for (int32_t j = W - 2; j >= 0; --j) /* backward */",
      "for (int32_t j = W - 2; j >= W; --j) /* backward */"),
-    ("chessboard takes the smaller offset", "(di > dj ? di : dj)", "(di < dj ? di : dj)"),
-    ("city-block squares the offsets", "? di + dj :", "? di * di + dj * dj :"),
+    ("chessboard takes the smaller offset", ": (metric == 2) ? hi", ": (metric == 2) ? lo"),
+    ("city-block squares the offsets", "(metric == 1) ? di + dj", "(metric == 1) ? di * di + dj * dj"),
+    ("chamfer swaps the diagonal and straight costs", ": 4 * lo + 3 * (hi - lo);",
+     ": 3 * lo + 4 * (hi - lo);"),
+    ("chamfer forward scan skips the upper-right neighbour",
+     "if (i > 0 && j + 1 < W) LOWER(i, j, AT(i - 1, j + 1) + 4);",
+     "if (i > 0 && j + 1 < 0) LOWER(i, j, AT(i - 1, j + 1) + 4);"),
+    ("chamfer backward diagonal step costs 3", "LOWER(i, j, AT(i + 1, j + 1) + 4);",
+     "LOWER(i, j, AT(i + 1, j + 1) + 3);"),
+    ("chamfer backward scan takes the rows top-down",
+     "for (int32_t i = H - 1; i >= 0; --i) { /* backward: bottom-right to top-left */",
+     "for (int32_t i = 0; i < H; ++i) { /* backward: bottom-right to top-left */"),
 ]
 
 
@@ -84,6 +94,13 @@ def _pins():
         yield TM.test_cityblock_scans_equal_definition, (seed,)
     for metric in (1, 2):
         yield TM.test_metric_closed_forms_and_invariants, (metric,)
+    for pol in (0, 1):
+        yield TM.test_chamfer_definition_matches_figure, (pol,)
+    yield TM.test_chamfer_forward_scan_matches_figure_but_the_erratum, ()
+    yield TM.test_chamfer_final_matches_figure, ()
+    for seed in range(4):
+        yield TM.test_chamfer_scans_equal_definition, (seed,)
+    yield TM.test_chamfer_bounds_against_euclidean, ()
 
 
 def _failures(lib):
