@@ -65,7 +65,10 @@ typedef int32_t edt_status;
 /* Metrics of the Minkowski family (Eq. eq_Minkowski, Section 1.3.1).  For the
  * squared Euclidean metric dist_sq holds d^2; for city-block (e = 1, d = |di| +
  * |dj|) and chessboard (e = infinity, d = max(|di|, |dj|)) it holds d itself.
- * The chamfer 4-3 approximation (Section 2.2) is reserved. */
+ * Chamfer 4-3 (Section 1.3.2, Eq. eq_rel; its transform in Section 2.2): the
+ * shortest path with steps of 3 horizontally and vertically and 4 diagonally,
+ * d = 3 max(|di|, |dj|) + min(|di|, |dj|) -- three times the approximate
+ * Euclidean distance, in integers. */
 #define EDT_METRIC_EUCLIDEAN_SQ 0
 #define EDT_METRIC_CITYBLOCK 1
 #define EDT_METRIC_CHESSBOARD 2
@@ -89,13 +92,14 @@ size_t edt_workspace_bytes(int32_t H, int32_t W, int32_t want_feature);
 /* Exact distance transform: squared Euclidean (Section 3: the vertical pass
  * of Section 3.1, then per row the lower envelope of parabolas of Section
  * 3.3.1, Eq. eq_parabola and Eq. eq_intersection), or city-block / chessboard
- * (the same two passes with the row costs |j - k| + |i - r| and max(|j - k|,
- * |i - r|) in place of the parabolas; equal to the propagation scans of
- * Section 2.1 for city-block).
+ * / chamfer 4-3 (the same two passes with the row costs |j - k| + |i - r|,
+ * max(|j - k|, |i - r|) and 3 max + min of the two in place of the parabolas;
+ * equal to the propagation scans of Section 2.1 for city-block and to the two
+ * raster scans of Section 2.2 for chamfer 4-3).
  *   mask        device, uint8, H x W with row pitch mask_pitch bytes
  *   polarity    EDT_TO_OBJECT or EDT_TO_BACKGROUND
- *   metric      EDT_METRIC_EUCLIDEAN_SQ, _CITYBLOCK or _CHESSBOARD
- *               (_CHAMFER34: EDT_ERR_UNSUPPORTED; other values: INVALID_ARG)
+ *   metric      EDT_METRIC_EUCLIDEAN_SQ, _CITYBLOCK, _CHESSBOARD or _CHAMFER34
+ *               (other values: EDT_ERR_INVALID_ARG)
  *   dist_sq     device, int32, H x W with row pitch out_pitch elements; written
  *   workspace   device, at least edt_workspace_bytes(H, W, 0) bytes, 256-byte
  *               aligned; contents on entry are ignored and on exit undefined
@@ -107,9 +111,9 @@ edt_status edt_sq(const uint8_t *mask, int32_t H, int32_t W, int64_t mask_pitch,
 
 /* Exact distance plus feature transform (the nearest site's index, Section
  * 3.3: the column that gives the minimum, extended with the site's row from
- * the vertical pass), for the squared Euclidean and the city-block metric
- * (chessboard: EDT_ERR_UNSUPPORTED, because its ties between sites of one
- * column are not decided by the vertical pass).  Same arguments as edt_sq, plus
+ * the vertical pass), for the squared Euclidean, city-block and chamfer 4-3
+ * metrics (chessboard: EDT_ERR_UNSUPPORTED, because its ties between sites of
+ * one column are not decided by the vertical pass).  Same arguments as edt_sq, plus
  *   dist_sq     may be NULL when only the features are wanted
  *   feature     device, int32, H x W with row pitch out_pitch elements; written */
 edt_status edt_feature(const uint8_t *mask, int32_t H, int32_t W,

@@ -127,7 +127,8 @@ def sq(mask: torch.Tensor, polarity: int = EDT_TO_OBJECT, metric: int = EDT_METR
        out: torch.Tensor | None = None, workspace: torch.Tensor | None = None,
        stream=None) -> torch.Tensor:
     """Distance of every pixel to the nearest site (int32): squared Euclidean
-    (metric 0), city-block (1) or chessboard (2)."""
+    (metric 0), city-block (1), chessboard (2) or chamfer 4-3 (3: three times
+    the approximate distance)."""
     mask = _check_mask(mask)
     H, W = mask.shape
     out = _check_out(out, H, W, mask.device, "out")

@@ -33,7 +33,6 @@ edt_status check_image(const uint8_t* mask, int32_t H, int32_t W, int64_t mask_p
     if (!mask || mask_pitch < W || out_pitch < W) return EDT_ERR_INVALID_ARG;
     if (polarity != EDT_TO_OBJECT && polarity != EDT_TO_BACKGROUND) return EDT_ERR_INVALID_ARG;
     if (metric < 0 || metric > EDT_METRIC_CHAMFER34) return EDT_ERR_INVALID_ARG;
-    if (metric == EDT_METRIC_CHAMFER34) return EDT_ERR_UNSUPPORTED;
     return EDT_OK;
 }
 

@@ -103,7 +103,8 @@ struct Img {
     int64_t opitch;    // elements between output rows
     uint8_t* ws;       // this image's workspace (layout_for(H, W))
     int H, W, pol;
-    int metric;        // EDT_METRIC_*: 0 squared Euclidean, 1 city-block, 2 chessboard
+    int metric;        // EDT_METRIC_*: 0 squared Euclidean, 1 city-block, 2 chessboard,
+                       // 3 chamfer 4-3
 };
 
 // Pointers into an image's workspace.

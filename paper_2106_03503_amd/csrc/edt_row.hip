@@ -45,13 +45,17 @@ __device__ __forceinline__ int crow(uint32_t c) { return (int)(c & 0xFFFFu); }
 
 // Distance from pixel (i, j) to the site of candidate C under metric kM: the
 // squared Euclidean distance (kM = 0, below 2^31 for sides up to 32767), the
-// city-block distance (1) or the chessboard distance (2).
+// city-block distance (1), the chessboard distance (2) or the chamfer 4-3
+// distance (3: min(|di|, |dj|) diagonal steps of 4 and the rest straight
+// steps of 3).
 template <int kM>
 __device__ __forceinline__ int dist_to(uint32_t C, int i, int j) {
     const int dr = i - crow(C), dc = j - ccol(C);
     if (kM == 0) return sqr_c(dr) + sqr_c(dc);
     const int ar = dr < 0 ? -dr : dr, ac = dc < 0 ? -dc : dc;
-    return kM == 1 ? ar + ac : max(ar, ac);
+    if (kM == 1) return ar + ac;
+    if (kM == 2) return max(ar, ac);
+    return 3 * max(ar, ac) + min(ar, ac);
 }
 
 // Does B (a column right of A's) beat A at pixel j of row i?
@@ -69,7 +73,7 @@ __device__ __forceinline__ bool beats(uint32_t B, uint32_t A, int i, int j) {
 //   City-block: with vertical offsets fa, fb, B wins left of both columns iff
 //   fb + l < fa + k (ties by index), right of both iff fb - l < fa - k, and in
 //   between from the first j with 2j > fb - fa + l + k.
-//   Chessboard: the suffix is found by bisection.
+//   Chessboard and chamfer 4-3: the suffix is found by bisection.
 template <int kM>
 __device__ __forceinline__ int first_win(uint32_t A, uint32_t B, int i, int W) {
     const int k = ccol(A), l = ccol(B), rk = crow(A), rl = crow(B);
@@ -678,6 +682,7 @@ hipError_t launch_rows_metric(const Img& g, uint8_t* slots, hipStream_t stream) 
 hipError_t launch_row_pass(const Img& g, uint8_t* slots, hipStream_t stream) {
     if (g.metric == 1) return launch_rows_metric<1>(g, slots, stream);
     if (g.metric == 2) return launch_rows_metric<2>(g, slots, stream);
+    if (g.metric == 3) return launch_rows_metric<3>(g, slots, stream);
     return launch_rows_metric<0>(g, slots, stream);
 }
 

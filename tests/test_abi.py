@@ -72,7 +72,8 @@ def test_argument_validation_returns_before_any_launch(edt):
     assert lib.edt_feature(fake, 10, 10, 10, 0, 0, fake, None, 10, fake, ws, None) == -1
     # enums
     assert lib.edt_sq(fake, 10, 10, 10, 2, 0, fake, 10, fake, ws, None) == -1
-    assert lib.edt_sq(fake, 10, 10, 10, 0, 3, fake, 10, fake, ws, None) == -2  # chamfer: reserved
+    assert lib.edt_sq(fake, 10, 10, 10, 0, 4, fake, 10, fake, ws, None) == -1  # past chamfer 4-3
+    assert lib.edt_sq(fake, 10, 10, 10, 0, -1, fake, 10, fake, ws, None) == -1
     # chessboard features are not provided
     assert lib.edt_feature(fake, 10, 10, 10, 0, 2, fake, fake, 10, fake, ws, None) == -2
     assert lib.edt_sq(fake, 10, 10, 10, 0, 9, fake, 10, fake, ws, None) == -1

@@ -1,6 +1,7 @@
-"""City-block and chessboard transforms on the GPU (edt_sq / edt_feature with
-EDT_METRIC_CITYBLOCK and EDT_METRIC_CHESSBOARD): bit-exact with the oracle's
-definition (O1) and, for city-block, with its four propagation scans."""
+"""City-block, chessboard and chamfer 4-3 transforms on the GPU (edt_sq /
+edt_feature with EDT_METRIC_CITYBLOCK, _CHESSBOARD and _CHAMFER34): bit-exact
+with the oracle's definition (O1) and, for city-block and chamfer 4-3, with
+the propagation scans of Sections 2.1 and 2.2."""
 import numpy as np
 import pytest
 
@@ -44,17 +45,44 @@ def _masks():
 MASKS = _masks()
 
 
-@pytest.mark.parametrize("metric", [1, 2])
+@pytest.mark.parametrize("metric", [1, 2, 3])
 @pytest.mark.parametrize("k", range(len(MASKS)), ids=[n for n, _ in MASKS])
 def test_metric_matches_definition(edt, metric, k):
     name, m = MASKS[k]
     for pol in (0, 1):
         Db, Fb = oracle.brute_metric(m, metric, pol)
-        D, F = _run(edt, m, pol, metric, feature=(metric == 1))
+        D, F = _run(edt, m, pol, metric, feature=(metric != 2))
         assert np.array_equal(D, Db), (name, pol)
-        if metric == 1:
+        if metric != 2:
             assert np.array_equal(F, Fb), (name, pol)
+        if metric == 1:
             assert np.array_equal(D, oracle.cityblock_scans(m, pol)), (name, pol)
+        if metric == 3:
+            assert np.array_equal(D, oracle.chamfer_scans(m, pol)), (name, pol)
+            assert np.array_equal(_run(edt, m, pol, metric, feature=False)[0], Db), (name, pol)
+
+
+def test_chamfer_paper_example_matches_figure(edt):
+    from tests.golden_io import table
+    D, _ = _run(edt, workloads.paper_example(), 0, 3, feature=True)
+    assert np.array_equal(D, table("fig_chamfer43dt_b.txt"))
+
+
+def test_chamfer_large_against_raster_scans(edt):
+    # sizes beyond the brute force: disks and points, both polarities, the
+    # oracle's two raster scans of Section 2.2 at 1024 x 1536
+    m = workloads.disks(1024, 1536, n_disks=40, rmin=5, rmax=80)
+    for pol in (0, 1):
+        D, F = _run(edt, m, pol, 3, feature=True)
+        assert np.array_equal(D, oracle.chamfer_scans(m, pol)), pol
+        # every feature is a site at the reported distance
+        H, W = m.shape
+        r, c = F // W, F % W
+        site = (m != 0) if pol == 0 else (m == 0)
+        assert site[r, c].all()
+        ii, jj = np.indices((H, W))
+        di, dj = np.abs(ii - r), np.abs(jj - c)
+        assert np.array_equal(3 * np.maximum(di, dj) + np.minimum(di, dj), D), pol
 
 
 def test_metric_errors(edt):
@@ -64,20 +92,17 @@ def test_metric_errors(edt):
         edt.feature(mt, metric=2)  # chessboard features: not decided by the vertical pass
     assert e.value.status == -2
     with pytest.raises(edt.EDTError) as e:
-        edt.sq(mt, metric=3)  # chamfer 4-3: reserved
-    assert e.value.status == -2
-    with pytest.raises(edt.EDTError) as e:
         edt.sq(mt, metric=4)
     assert e.value.status == -1
 
 
-def test_wide_rows_chessboard_and_cityblock(edt):
+def test_wide_rows_chessboard_cityblock_chamfer(edt):
     """Rows wider than the LDS forms take (the global-slot form)."""
     rng = np.random.default_rng(2106302)
     m = (rng.random((6, 20000)) < 0.002).astype(np.uint8)
-    for metric in (1, 2):
+    for metric in (1, 2, 3):
         Db, Fb = oracle.brute_metric(m, metric, 0)
-        D, F = _run(edt, m, 0, metric, feature=(metric == 1))
+        D, F = _run(edt, m, 0, metric, feature=(metric != 2))
         assert np.array_equal(D, Db)
-        if metric == 1:
+        if metric != 2:
             assert np.array_equal(F, Fb)
