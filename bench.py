@@ -7,6 +7,8 @@ Workloads (--workload):
                        which the HBM roofline is measured;
   points16k_sq         the same image through edt_sq (distances only);
   disks4k, disks4k_inside, bernoulli256
+  disks4k_chamfer      the disks image through edt_sq with the chamfer 4-3 metric,
+                       with its error against the exact Euclidean distance
                        other single images (4096^2 disks outside / inside,
                        256^2 Bernoulli(0.01));
   batch2048            one step = one edt_batch_submit over 2048 images of
@@ -91,6 +93,10 @@ SINGLE = {
     "bernoulli256": dict(
         H=256, W=256, polarity=0,
         desc="256x256 uint8 mask, Bernoulli(0.01) object pixels"),
+    "disks4k_chamfer": dict(
+        H=4096, W=4096, polarity=0, call="edt_sq", metric=3,
+        desc="4096x4096 uint8 mask, 200 random filled disks (r 5-200) + Bernoulli(1e-4) "
+             "points; int32 chamfer 4-3 distances (scaled by 3) outside objects (edt_sq)"),
 }
 BATCH_DESC = ("2048 uint8 masks of uneven size (H, W uniform in 64..1024), 5-60 overlapping "
               "random ellipses each (semi-axes 4-80), polarity Bernoulli(0.5); int32 squared "
@@ -154,20 +160,48 @@ def cpu_threads() -> int:
     return oracle.default_threads()
 
 
-def cpu_baseline(images, units_px):
-    """The oracle's separable transform over the images, on the host cores."""
+def cpu_baseline(images, units_px, metric=0):
+    """The oracle over the images on the host cores: its separable transform,
+    or for the chamfer 4-3 metric its two raster scans (one thread)."""
     import oracle
-    threads = cpu_threads()
+    threads = cpu_threads() if metric == 0 else 1
     t0 = time.perf_counter()
     for m, pol in images:
-        oracle.separable(m, pol, nthreads=threads)
+        if metric == 3:
+            oracle.chamfer_scans(m, pol)
+        else:
+            oracle.separable(m, pol, nthreads=threads)
     dt = time.perf_counter() - t0
     what = (f"the whole {images[0][0].shape[0]}x{images[0][0].shape[1]} image" if len(images) == 1
             else f"all {len(images)} images of the batch, one after the other")
+    how = ("the oracle's two raster scans of the chamfer 4-3 transform" if metric == 3 else
+           "the oracle's separable transform (vertical pass + lower envelope + fill)")
     return {"value": round(units_px / dt / 1e9, 5), "unit": "Gpixel/s", "cores": threads,
             "kind": "oracle",
-            "sample": f"one full pass of the oracle's separable transform (vertical pass + lower "
-                      f"envelope + fill) over {what}, {threads} POSIX threads, {dt:.2f} s"}
+            "sample": f"one full pass of {how} over {what}, {threads} thread(s), {dt:.2f} s"}
+
+
+def approx_error(mask, pol, D, ws, stream):
+    """Chamfer 4-3 distance / 3 against the exact Euclidean distance of the
+    same image (computed once by edt_sq, outside the timed region), over the
+    pixels that have a site: mean and largest absolute error in pixels, the
+    range of the relative error, and the share of pixels where they differ."""
+    import torch
+    import paper_2106_03503_amd as edt
+    E = edt.sq(mask, polarity=pol, workspace=ws, stream=stream)
+    ok = E != edt.EDT_INF_SQ
+    c = D[ok].double() / 3.0
+    e = E[ok].double().sqrt()
+    err = c - e
+    pos = e > 0
+    rel = err[pos] / e[pos]
+    out = {"vs": "exact Euclidean distance (edt_sq, squared Euclidean metric)",
+           "mean_abs_px": round(float(err.abs().mean()), 4),
+           "max_abs_px": round(float(err.abs().max()), 4),
+           "rel_min": round(float(rel.min()), 4), "rel_max": round(float(rel.max()), 4),
+           "frac_differs": round(float((err.abs() > 1e-9).double().mean()), 4)}
+    torch.cuda.synchronize()
+    return out
 
 
 def copy_calibration(steps):
@@ -238,18 +272,22 @@ def run_single(args):
     stream = torch.cuda.current_stream()
 
     sq_only = wl.get("call") == "edt_sq"
+    metric = wl.get("metric", 0)
 
     def step():
         if sq_only:
-            edt.sq(mask, polarity=pol, out=D, workspace=ws, stream=stream)
+            edt.sq(mask, polarity=pol, metric=metric, out=D, workspace=ws, stream=stream)
         else:
-            edt.feature(mask, polarity=pol, out_dist=D, out_feat=F, workspace=ws, stream=stream)
+            edt.feature(mask, polarity=pol, metric=metric, out_dist=D, out_feat=F, workspace=ws,
+                        stream=stream)
 
     ms, kt = timed(step, args.steps, args.warmup)
     px = H * W
     out = base_line(args, px / (ms * 1e-3) / 1e9, ms,
                     {"workload": wl["desc"], "H": H, "W": W, "polarity": pol,
                      "call": "edt_sq" if sq_only else "edt_feature",
+                     "metric": ["squared Euclidean", "city-block", "chessboard",
+                                "chamfer 4-3"][metric],
                      "parallelism": "single GPU"})
     out["roofline"] = roofline(kt, lambda k: algo_bytes(k, H, W, n, with_dist=not sq_only),
                                args.workload)
@@ -258,8 +296,10 @@ def run_single(args):
     out["path_hbm"] = {"bytes_per_px": path_b, "achieved_GBs": round(gbs, 1),
                        "frac": round(gbs / HBM_PEAK_GBS, 4)}
     out["kernels_ms_per_step"] = {k: round(v[1] / args.steps, 4) for k, v in sorted(kt.items())}
+    if metric == 3:
+        out["approx_error"] = approx_error(mask, pol, D, ws, stream)
     if not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline([(mask_np, pol)], px)
+        out["cpu_baseline"] = cpu_baseline([(mask_np, pol)], px, metric)
     return out
 
 
