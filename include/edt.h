@@ -16,7 +16,10 @@
  *     1 <= H, W <= EDT_MAX_SIDE.  Row i, column j are 0-based.
  *   - Mask: uint8, byte 0 = background, any other value = object pixel
  *     (Section 1.1: a binary image holds one of two values per pixel).
- *     mask_pitch is the distance in BYTES between row starts (>= W).
+ *     mask_pitch is the distance in BYTES between row starts (>= W).  Mask
+ *     rows are read in whole aligned 4-byte words: the bytes of such a word
+ *     that lie before a row's first or after its last pixel (at most 3 on
+ *     either side, never on another page) are read and ignored.
  *   - polarity EDT_TO_OBJECT: sites are the object pixels, i.e. every pixel
  *     gets its distance to the nearest object pixel (Figure fig_examples(c));
  *     EDT_TO_BACKGROUND: sites are the background pixels (Figure
