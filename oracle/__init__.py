@@ -72,6 +72,8 @@ def bind(path: str):
     lib.oracle_brute_metric.restype = i64
     lib.oracle_chamfer_scans.argtypes = [P, i32, i32, i64, i32, i32, P]
     lib.oracle_chamfer_scans.restype = None
+    lib.oracle_regions.argtypes = [P, i32, i32, i64, i32, i32, P, P]
+    lib.oracle_regions.restype = None
     lib.oracle_cityblock_scans.argtypes = [P, i32, i32, i64, i32, i32, P]
     lib.oracle_cityblock_scans.restype = None
     return lib
@@ -224,3 +226,17 @@ def chamfer_scans(mask, polarity: int = 0, passes: int = 2):
     D = np.empty((H, W), np.int32)
     _load().oracle_chamfer_scans(_ptr(m), H, W, W, polarity, passes, _ptr(D))
     return D
+
+
+def regions(mask, F, polarity: int = 0, connectivity: int = 8):
+    """Region label of every pixel: the smallest linear index of the connected
+    component (4- or 8-neighbourhood) of sites that holds its nearest site F;
+    -1 where F is -1."""
+    m = _mask(mask)
+    H, W = m.shape
+    f = np.ascontiguousarray(np.asarray(F, dtype=np.int32))
+    if f.shape != (H, W):
+        raise ValueError("F must have the mask's shape")
+    L = np.empty((H, W), np.int32)
+    _load().oracle_regions(_ptr(m), H, W, W, polarity, connectivity, _ptr(f), _ptr(L))
+    return L

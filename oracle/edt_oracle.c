@@ -45,6 +45,9 @@
  *                        forward and backward, one comparison per pixel each).
  *   oracle_chamfer_scans the chamfer 4-3 transform by the two raster scans of
  *                        Section 2.2 (four comparisons per pixel and scan).
+ *   oracle_regions       Voronoi regions of the connected objects (Section
+ *                        1.1 with the neighbourhoods of Section 1.2): the
+ *                        component of each pixel's nearest site.
  *
  * Integer arithmetic is done in int64 throughout; nothing here is tuned.
  */
@@ -603,4 +606,53 @@ void oracle_chamfer_scans(const uint8_t *mask, int32_t H, int32_t W, int64_t pit
     for (int64_t q = 0; q < (int64_t)H * W; ++q)
         D[q] = d[q] >= big ? ORACLE_INF_SQ : (int32_t)d[q];
     free(d);
+}
+
+/* ------------------------------------------------------- region labels */
+
+/* Voronoi regions of the objects (Section 1.1: after the transform each region
+ * stands for one object point or one cluster of connected points, Figures
+ * fig_voronoi and fig_blobs).  The sites are grouped into connected components
+ * under the 4- or the 8-neighbourhood of Section 1.2 by a breadth-first flood
+ * fill started from each unlabelled site in raster order, so that a
+ * component's label is the linear index r*W + c of its first site in raster
+ * order, the smallest.  Every pixel then takes the label of the component
+ * that holds its nearest site F (the feature transform); pixels of an image
+ * without sites (F = -1) get -1.  F is row-major with row pitch W. */
+void oracle_regions(const uint8_t *mask, int32_t H, int32_t W, int64_t pitch,
+                    int32_t polarity, int32_t connectivity, const int32_t *F,
+                    int32_t *labels)
+{
+    const int64_t n = (int64_t)H * W;
+    int32_t *comp = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
+    int64_t *queue = (int64_t *)malloc(sizeof(int64_t) * (size_t)n);
+    for (int64_t q = 0; q < n; ++q) comp[q] = -1;
+    for (int32_t i0 = 0; i0 < H; ++i0) {
+        for (int32_t j0 = 0; j0 < W; ++j0) {
+            const int64_t start = (int64_t)i0 * W + j0;
+            if (comp[start] >= 0 || !is_site(mask[(int64_t)i0 * pitch + j0], polarity)) continue;
+            int64_t head = 0, tail = 0;
+            comp[start] = (int32_t)start;
+            queue[tail++] = start;
+            while (head < tail) {
+                const int64_t cur = queue[head++];
+                const int32_t i = (int32_t)(cur / W), j = (int32_t)(cur % W);
+                for (int32_t di = -1; di <= 1; ++di) {
+                    for (int32_t dj = -1; dj <= 1; ++dj) {
+                        if (di == 0 && dj == 0) continue;
+                        if (connectivity == 4 && di != 0 && dj != 0) continue;
+                        const int32_t a = i + di, b = j + dj;
+                        if (a < 0 || a >= H || b < 0 || b >= W) continue;
+                        const int64_t nb = (int64_t)a * W + b;
+                        if (comp[nb] >= 0 || !is_site(mask[(int64_t)a * pitch + b], polarity)) continue;
+                        comp[nb] = (int32_t)start;
+                        queue[tail++] = nb;
+                    }
+                }
+            }
+        }
+    }
+    for (int64_t q = 0; q < n; ++q) labels[q] = F[q] < 0 ? -1 : comp[F[q]];
+    free(queue);
+    free(comp);
 }

@@ -11,6 +11,7 @@ import pytest
 import oracle
 from tests import test_oracle as T
 from tests import test_oracle_metrics as TM
+from tests import test_oracle_regions as TR
 
 MUTANTS = [
     ("tie rule reversed", "l_wins_tie = fl < fk;", "l_wins_tie = fl > fk;"),
@@ -63,6 +64,16 @@ MUTANTS = [
     ("chamfer backward scan takes the rows top-down",
      "for (int32_t i = H - 1; i >= 0; --i) { /* backward: bottom-right to top-left */",
      "for (int32_t i = 0; i < H; ++i) { /* backward: bottom-right to top-left */"),
+    ("regions drop the diagonal neighbours of the 8-neighbourhood",
+     "if (connectivity == 4 && di != 0 && dj != 0) continue;", "if (di != 0 && dj != 0) continue;"),
+    ("regions keep the diagonal neighbours in the 4-neighbourhood",
+     "if (connectivity == 4 && di != 0 && dj != 0) continue;", "if (connectivity == 5) continue;"),
+    ("regions label a component by the site it was reached from",
+     "comp[nb] = (int32_t)start;", "comp[nb] = (int32_t)cur;"),
+    ("regions label the pixel's own component, not its nearest site's",
+     "labels[q] = F[q] < 0 ? -1 : comp[F[q]];", "labels[q] = F[q] < 0 ? -1 : (comp[q] >= 0 ? comp[q] : F[q]);"),
+    ("regions search only upwards", "for (int32_t di = -1; di <= 1; ++di) {",
+     "for (int32_t di = -1; di <= 0; ++di) {"),
 ]
 
 
@@ -101,6 +112,12 @@ def _pins():
     for seed in range(4):
         yield TM.test_chamfer_scans_equal_definition, (seed,)
     yield TM.test_chamfer_bounds_against_euclidean, ()
+    yield TR.test_diagonal_pair_is_one_object_in_8_and_two_in_4, ()
+    yield TR.test_checkerboards, ()
+    yield TR.test_full_empty_and_isolated_points, ()
+    yield TR.test_paper_example_components, ()
+    for seed in range(4):
+        yield TR.test_regions_against_min_propagation, (seed,)
 
 
 def _failures(lib):
