@@ -7,6 +7,7 @@ Workloads (--workload):
                        which the HBM roofline is measured;
   points16k_sq         the same image through edt_sq (distances only);
   disks4k, disks4k_inside, bernoulli256
+  disks4k_regions      the disks image through edt_feature and then edt_regions
   disks4k_chamfer      the disks image through edt_sq with the chamfer 4-3 metric,
                        with its error against the exact Euclidean distance
                        other single images (4096^2 disks outside / inside,
@@ -59,6 +60,10 @@ def algo_bytes(kernel: str, H: int, W: int, n: int, with_dist: bool = True) -> i
         return nb * n * 12 + H * n * 2
     if kernel == "k_row_segscan":        # int16 rows in (segment envelopes stay on chip or spill)
         return H * n * 2
+    if kernel in ("k_reg_init", "k_reg_union", "k_reg_flatten", "k_reg_sites"):
+        return H * W                     # the mask (site slots are a small part)
+    if kernel == "k_reg_others":         # mask and F in, labels out
+        return H * W * 9
     if kernel == "k_row_segfill":        # int32 D and F (or D only) out
         return H * W * (8 if with_dist else 4)
     if kernel.startswith("k_row_"):      # int16 rows in, int32 D and F (or D only) out
@@ -93,6 +98,11 @@ SINGLE = {
     "bernoulli256": dict(
         H=256, W=256, polarity=0,
         desc="256x256 uint8 mask, Bernoulli(0.01) object pixels"),
+    "disks4k_regions": dict(
+        H=4096, W=4096, polarity=0, regions=8,
+        desc="4096x4096 uint8 mask, 200 random filled disks (r 5-200) + Bernoulli(1e-4) "
+             "points; int32 squared distance + nearest-object index (edt_feature), then the "
+             "Voronoi region of every pixel under 8-neighbourhood (edt_regions)"),
     "disks4k_chamfer": dict(
         H=4096, W=4096, polarity=0, call="edt_sq", metric=3,
         desc="4096x4096 uint8 mask, 200 random filled disks (r 5-200) + Bernoulli(1e-4) "
@@ -126,6 +136,8 @@ KERNEL_SOURCES = {
     "k_row_dense_global": ("edt_row.hip",), "k_row_lanes": ("edt_row_lanes.hip",),
     "k_row_segscan": ("edt_row_lanes.hip",), "k_row_segfill": ("edt_row.hip",),
     "k_sqrt": ("edt_api.hip",),
+    **{k: ("edt_regions.hip",) for k in ("k_reg_init", "k_reg_union", "k_reg_flatten",
+                                         "k_reg_others", "k_reg_sites")},
 }
 
 
@@ -274,18 +286,24 @@ def run_single(args):
     sq_only = wl.get("call") == "edt_sq"
     metric = wl.get("metric", 0)
 
+    conn = wl.get("regions", 0)
+    L = torch.empty((H, W), dtype=torch.int32, device=dev) if conn else None
+
     def step():
         if sq_only:
             edt.sq(mask, polarity=pol, metric=metric, out=D, workspace=ws, stream=stream)
         else:
             edt.feature(mask, polarity=pol, metric=metric, out_dist=D, out_feat=F, workspace=ws,
                         stream=stream)
+        if conn:
+            edt.regions(mask, F, polarity=pol, connectivity=conn, out=L, stream=stream)
 
     ms, kt = timed(step, args.steps, args.warmup)
     px = H * W
     out = base_line(args, px / (ms * 1e-3) / 1e9, ms,
                     {"workload": wl["desc"], "H": H, "W": W, "polarity": pol,
-                     "call": "edt_sq" if sq_only else "edt_feature",
+                     "call": ("edt_sq" if sq_only else "edt_feature")
+                             + (f" + edt_regions ({conn}-neighbourhood)" if conn else ""),
                      "metric": ["squared Euclidean", "city-block", "chessboard",
                                 "chamfer 4-3"][metric],
                      "parallelism": "single GPU"})

@@ -124,6 +124,30 @@ edt_status edt_feature(const uint8_t *mask, int32_t H, int32_t W,
                        int32_t *dist_sq, int32_t *feature, int64_t out_pitch,
                        void *workspace, size_t workspace_bytes, void *stream);
 
+/* Voronoi regions of the objects (Section 1.1: after the transform each region
+ * stands for one object point or one cluster of connected points, Figures
+ * fig_voronoi and fig_blobs).  The sites are grouped into connected components
+ * under the 4- or 8-neighbourhood of Section 1.2; every pixel gets the label of
+ * the component holding its nearest site, a component's label being the
+ * smallest linear index r*W + c of its sites.
+ *   mask, H, W, mask_pitch, polarity   the image and its sites, as for
+ *               edt_feature
+ *   connectivity 4 or 8
+ *   feature     device, int32, H x W with row pitch out_pitch elements: the
+ *               feature transform of this mask and polarity (edt_feature's
+ *               output, any metric); read only.  Other contents give
+ *               unspecified labels but no access outside the buffers.
+ *   labels      device, int32, H x W with row pitch out_pitch elements;
+ *               written, EDT_NO_SITE where the image holds no site.  It holds
+ *               the union-find forest of the sites during the call, so it may
+ *               not overlap mask or feature (EDT_ERR_INVALID_ARG).
+ * No workspace.  EDT_ERR_TOO_LARGE for sides outside [1, EDT_MAX_SIDE] or
+ * H * out_pitch >= 2^31; EDT_ERR_INVALID_ARG for null pointers, pitches below
+ * W, or a connectivity other than 4 or 8. */
+edt_status edt_regions(const uint8_t *mask, int32_t H, int32_t W, int64_t mask_pitch,
+                       int32_t polarity, int32_t connectivity, const int32_t *feature,
+                       int32_t *labels, int64_t out_pitch, void *stream);
+
 /* d = sqrt(D) drawn after all squared distances are known (Section 3.1):
  * computed in fp64 and rounded to fp32 (the nearest fp32 to the true root for
  * every D < 2^31); EDT_INF_SQ maps to +infinity.  dist_sq and dist are device

@@ -9,10 +9,12 @@ transform runs in the library's HIP kernels; there is no fallback.
     D = edt.sq(mask)                 # int32 squared distances
     D, F = edt.feature(mask)         # + nearest-site linear index
     d = edt.sqrt_f32(D)              # float32 distances
+    L = edt.regions(mask, F)         # Voronoi regions of the connected objects
     srv = edt.Server(1 << 30)        # request server: submit / wait / stats
 """
 from ._lib import (  # noqa: F401
     EDT_INF_SQ,
+    EDT_METRIC_CHAMFER34,
     EDT_METRIC_CHESSBOARD,
     EDT_METRIC_CITYBLOCK,
     EDT_METRIC_EUCLIDEAN_SQ,
@@ -27,6 +29,7 @@ from ._lib import (  # noqa: F401
     library_path,
     profile_begin,
     profile_end,
+    regions,
     sq,
     sqrt_f32,
     workspace_bytes,

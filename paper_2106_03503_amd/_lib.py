@@ -51,6 +51,8 @@ def _load():
     lib.edt_feature.restype = i32
     lib.edt_sqrt_f32.argtypes = [P, P, i64, P]
     lib.edt_sqrt_f32.restype = i32
+    lib.edt_regions.argtypes = [P, i32, i32, i64, i32, i32, P, P, i64, P]
+    lib.edt_regions.restype = i32
     lib.edt_profile_begin.argtypes = []
     lib.edt_profile_begin.restype = i32
     lib.edt_profile_end.argtypes = [P, i32, P]
@@ -171,6 +173,30 @@ def sqrt_f32(dist_sq: torch.Tensor, out: torch.Tensor | None = None, stream=None
         raise ValueError("out must be a contiguous float32 tensor of the same shape")
     _check(_lib.edt_sqrt_f32(dist_sq.data_ptr(), out.data_ptr(), dist_sq.numel(),
                              _stream_ptr(stream)), "edt_sqrt_f32")
+    return out
+
+
+def regions(mask: torch.Tensor, feature: torch.Tensor, polarity: int = EDT_TO_OBJECT,
+            connectivity: int = 8, out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+    """Voronoi region of every pixel (int32): the smallest linear index of the
+    connected component (4- or 8-neighbourhood) of sites that holds its
+    nearest site; ``feature`` is edt.feature's output for the same mask and
+    polarity."""
+    mask = _check_mask(mask)
+    H, W = mask.shape
+    if feature.dtype != torch.int32 or feature.shape != (H, W) or feature.stride(1) != 1 \
+            or feature.device != mask.device:
+        raise ValueError(f"feature must be an int32 {H}x{W} tensor on {mask.device}")
+    if out is None:
+        out = torch.empty_strided((H, W), (feature.stride(0), 1), dtype=torch.int32,
+                                  device=mask.device)
+    else:
+        out = _check_out(out, H, W, mask.device, "out")
+        if out.stride(0) != feature.stride(0):
+            raise ValueError("out and feature must share one row pitch")
+    _check(_lib.edt_regions(mask.data_ptr(), H, W, mask.stride(0), polarity, connectivity,
+                            feature.data_ptr(), out.data_ptr(), feature.stride(0),
+                            _stream_ptr(stream)), "edt_regions")
     return out
 
 

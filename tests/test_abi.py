@@ -81,6 +81,20 @@ def test_argument_validation_returns_before_any_launch(edt):
     assert lib.edt_sq(fake, 10, 10, 10, 0, 0, fake, 10, fake, ws - 1, None) == -1
     assert lib.edt_sq(fake, 10, 10, 10, 0, 0, fake, 10, None, ws, None) == -1
     assert lib.edt_sq(fake, 10, 10, 10, 0, 0, fake, 10, fake + 8, ws, None) == -1
+    # region labels: sizes, pointers, pitches, enums, overlap of labels with the inputs
+    big = 0x10000000
+    assert lib.edt_regions(fake, 0, 10, 10, 0, 8, fake, big, 10, None) == -3
+    assert lib.edt_regions(fake, 10, 40000, 40000, 0, 8, fake, big, 40000, None) == -3
+    assert lib.edt_regions(fake, 30000, 30000, 30000, 0, 8, fake, big, 80000, None) == -3
+    assert lib.edt_regions(None, 10, 10, 10, 0, 8, fake, big, 10, None) == -1
+    assert lib.edt_regions(fake, 10, 10, 10, 0, 8, None, big, 10, None) == -1
+    assert lib.edt_regions(fake, 10, 10, 10, 0, 8, fake, None, 10, None) == -1
+    assert lib.edt_regions(fake, 10, 10, 9, 0, 8, fake, big, 10, None) == -1
+    assert lib.edt_regions(fake, 10, 10, 10, 0, 8, fake, big, 9, None) == -1
+    assert lib.edt_regions(fake, 10, 10, 10, 2, 8, fake, big, 10, None) == -1
+    assert lib.edt_regions(fake, 10, 10, 10, 0, 6, fake, big, 10, None) == -1
+    assert lib.edt_regions(fake, 10, 10, 10, 0, 8, big + 40, big, 10, None) == -1  # labels over feature
+    assert lib.edt_regions(big + 4, 10, 10, 10, 0, 8, fake, big, 10, None) == -1   # labels over mask
     # sqrt
     assert lib.edt_sqrt_f32(fake, fake, -1, None) == -1
     assert lib.edt_sqrt_f32(None, fake, 5, None) == -1
