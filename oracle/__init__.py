@@ -74,6 +74,8 @@ def bind(path: str):
     lib.oracle_chamfer_scans.restype = None
     lib.oracle_regions.argtypes = [P, i32, i32, i64, i32, i32, P, P]
     lib.oracle_regions.restype = None
+    lib.oracle_danielsson.argtypes = [P, i32, i32, i64, i32, i32, P, P]
+    lib.oracle_danielsson.restype = None
     lib.oracle_cityblock_scans.argtypes = [P, i32, i32, i64, i32, i32, P]
     lib.oracle_cityblock_scans.restype = None
     return lib
@@ -240,3 +242,15 @@ def regions(mask, F, polarity: int = 0, connectivity: int = 8):
     L = np.empty((H, W), np.int32)
     _load().oracle_regions(_ptr(m), H, W, W, polarity, connectivity, _ptr(f), _ptr(L))
     return L
+
+
+def danielsson(mask, polarity: int = 0, passes: int = 2):
+    """Danielsson's approximate transform (Section 2.3): (D, R) with D = dy^2 +
+    dx^2 and R = (dy << 16) | dx the propagated relative position (INT32_MAX
+    and -1 where unreached); passes=1 stops after the first scan."""
+    m = _mask(mask)
+    H, W = m.shape
+    D = np.empty((H, W), np.int32)
+    R = np.empty((H, W), np.int32)
+    _load().oracle_danielsson(_ptr(m), H, W, W, polarity, passes, _ptr(D), _ptr(R))
+    return D, R

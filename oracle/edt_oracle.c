@@ -48,6 +48,8 @@
  *   oracle_regions       Voronoi regions of the connected objects (Section
  *                        1.1 with the neighbourhoods of Section 1.2): the
  *                        component of each pixel's nearest site.
+ *   oracle_danielsson    Danielsson's approximate transform by propagation of
+ *                        relative positions, two scans (Section 2.3).
  *
  * Integer arithmetic is done in int64 throughout; nothing here is tuned.
  */
@@ -655,4 +657,87 @@ void oracle_regions(const uint8_t *mask, int32_t H, int32_t W, int64_t pitch,
     for (int64_t q = 0; q < n; ++q) labels[q] = F[q] < 0 ? -1 : comp[F[q]];
     free(queue);
     free(comp);
+}
+
+/* ------------------------------------------------------------ Danielsson */
+
+/* Danielsson's approximate transform in the two-scan form of Section 2.3 (after
+ * Grevera): every pixel keeps a relative position (dy, dx) -- magnitudes of
+ * the vertical and horizontal offset to the site it was reached from -- and
+ * d^2 = dy^2 + dx^2.  Sites start at (0, 0), every other pixel unreached.  A
+ * neighbour that has been reached offers its position with one added to dy
+ * for a vertical step, to dx for a horizontal step and to both for a diagonal
+ * one; the pixel takes the offer when it is strictly nearer than what it
+ * holds.  The first scan takes the rows from the second one down: per row,
+ * first every pixel's upper neighbour, then left to right the left and the
+ * upper-left neighbour, then right to left the upper-right and the right
+ * neighbour.  The second scan takes the rows from the second-last one up,
+ * mirrored: every pixel's lower neighbour, then left to right the left and
+ * the lower-left neighbour, then right to left the right and the lower-right
+ * neighbour.  passes = 1 stops after the first scan (Figure
+ * fig_DanielssonDT(b)), passes = 2 gives the result (Figure
+ * fig_DanielssonDT(c)).  Outputs: D = d^2 (INT32_MAX where unreached) and
+ * R = (dy << 16) | dx (-1 where unreached), row-major with pitch W. */
+static void dan_offer(int64_t *d, int32_t *y, int32_t *x, int64_t to, int64_t from,
+                      int32_t ay, int32_t ax)
+{
+    if (y[from] < 0) return; /* nothing to propagate */
+    const int32_t ny = y[from] + ay, nx = x[from] + ax;
+    const int64_t nd = (int64_t)ny * ny + (int64_t)nx * nx;
+    if (d[to] > nd) {
+        d[to] = nd;
+        y[to] = ny;
+        x[to] = nx;
+    }
+}
+
+void oracle_danielsson(const uint8_t *mask, int32_t H, int32_t W, int64_t pitch,
+                       int32_t polarity, int32_t passes, int32_t *D, int32_t *R)
+{
+    const int64_t n = (int64_t)H * W;
+    const int64_t unreached = INT64_MAX;
+    int64_t *d = (int64_t *)malloc(sizeof(int64_t) * (size_t)n);
+    int32_t *y = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
+    int32_t *x = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
+    for (int32_t i = 0; i < H; ++i)
+        for (int32_t j = 0; j < W; ++j) {
+            const int64_t o = (int64_t)i * W + j;
+            const int s = is_site(mask[(int64_t)i * pitch + j], polarity);
+            d[o] = s ? 0 : unreached;
+            y[o] = s ? 0 : -1;
+            x[o] = s ? 0 : -1;
+        }
+#define P(i, j) ((int64_t)(i) * W + (j))
+    for (int32_t i = 1; i < H; ++i) { /* first scan, downwards */
+        for (int32_t j = 0; j < W; ++j) dan_offer(d, y, x, P(i, j), P(i - 1, j), 1, 0);
+        for (int32_t j = 1; j < W; ++j) {
+            dan_offer(d, y, x, P(i, j), P(i, j - 1), 0, 1);
+            dan_offer(d, y, x, P(i, j), P(i - 1, j - 1), 1, 1);
+        }
+        for (int32_t j = W - 2; j >= 0; --j) {
+            dan_offer(d, y, x, P(i, j), P(i - 1, j + 1), 1, 1);
+            dan_offer(d, y, x, P(i, j), P(i, j + 1), 0, 1);
+        }
+    }
+    if (passes >= 2) {
+        for (int32_t i = H - 2; i >= 0; --i) { /* second scan, upwards */
+            for (int32_t j = 0; j < W; ++j) dan_offer(d, y, x, P(i, j), P(i + 1, j), 1, 0);
+            for (int32_t j = 1; j < W; ++j) {
+                dan_offer(d, y, x, P(i, j), P(i, j - 1), 0, 1);
+                dan_offer(d, y, x, P(i, j), P(i + 1, j - 1), 1, 1);
+            }
+            for (int32_t j = W - 2; j >= 0; --j) {
+                dan_offer(d, y, x, P(i, j), P(i, j + 1), 0, 1);
+                dan_offer(d, y, x, P(i, j), P(i + 1, j + 1), 1, 1);
+            }
+        }
+    }
+#undef P
+    for (int64_t o = 0; o < n; ++o) {
+        D[o] = y[o] < 0 ? ORACLE_INF_SQ : (int32_t)d[o];
+        R[o] = y[o] < 0 ? -1 : (int32_t)(((uint32_t)y[o] << 16) | (uint32_t)x[o]);
+    }
+    free(x);
+    free(y);
+    free(d);
 }

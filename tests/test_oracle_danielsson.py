@@ -1,0 +1,99 @@
+"""Pins of the oracle's Danielsson transform (Section 2.3): the printed relative
+positions of the worked example after the first scan and at the end (one
+erratum cell), the text's statement that this example reaches the exact
+distances, and what the mathematics fixes on any mask: every stored position
+is a site's offset bound from above (so d^2 is never below the exact value),
+0 exactly at the sites, single sites exact (images of two rows or more), and
+a three-site configuration whose disconnected Voronoi region the propagation
+cannot reach (the failure Figure fig_propError describes)."""
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+from tests.golden_io import GOLDEN
+
+INF_SQ = oracle.INF_SQ
+# three object pixels in a 32 x 32 image where the propagation misses the
+# nearest site at pixel (2, 3) (found by searching random configurations)
+MISSED_SITES = [(13, 29), (6, 31), (22, 23)]
+MISSED_PIXEL = (2, 3)
+
+
+def positions(name):
+    rows = []
+    with open(os.path.join(GOLDEN, name)) as f:
+        for line in f:
+            line = line.split("#", 1)[0].split()
+            if line:
+                rows.append([-1 if v == "inf" else (int(v.split(",")[0]) << 16) | int(v.split(",")[1])
+                             for v in line])
+    return np.array(rows, dtype=np.int64)
+
+
+def missed_mask():
+    m = np.zeros((32, 32), np.uint8)
+    for r, c in MISSED_SITES:
+        m[r, c] = 1
+    return m
+
+
+def test_first_scan_matches_figure():
+    _, R = oracle.danielsson(workloads.paper_example(), passes=1)
+    assert np.array_equal(R, positions("fig_danielssondt_b.txt"))
+
+
+def test_final_matches_figure_but_the_erratum():
+    m = workloads.paper_example()
+    D, R = oracle.danielsson(m)
+    want = positions("fig_danielssondt_c.txt")
+    ok = np.ones(want.shape, bool)
+    ok[2, 2] = False  # printed 1,1; no object pixel lies at that offset
+    assert np.array_equal(R[ok], want[ok])
+    assert R[2, 2] in ((1 << 16) | 2, (2 << 16) | 1)
+    # "for the given example, this corresponds to the exact Euclidean distances"
+    assert np.array_equal(D, oracle.separable(m)[0])
+
+
+@pytest.mark.parametrize("seed", range(8))
+def test_never_below_exact_and_consistent(seed):
+    rng = np.random.default_rng(700 + seed)
+    H, W = int(rng.integers(2, 50)), int(rng.integers(1, 50))
+    m = (rng.random((H, W)) < rng.choice([0.0, 0.003, 0.02, 0.2, 0.6])).astype(np.uint8)
+    for pol in (0, 1):
+        D, R = oracle.danielsson(m, pol)
+        E, _ = oracle.separable(m, pol)
+        site = (m != 0) if pol == 0 else (m == 0)
+        if not site.any():
+            assert (D == INF_SQ).all() and (R == -1).all()
+            continue
+        dy, dx = R >> 16, R & 0xFFFF
+        assert (R >= 0).all()
+        assert np.array_equal(D.astype(np.int64), dy.astype(np.int64) ** 2 + dx.astype(np.int64) ** 2)
+        assert ((D == 0) == site).all()
+        assert (D >= E).all()
+        assert (dy <= H - 1).all() and (dx <= W - 1).all()
+
+
+def test_single_sites_exact_and_one_row_propagates_nothing():
+    rng = np.random.default_rng(9)
+    for _ in range(40):
+        H, W = int(rng.integers(2, 30)), int(rng.integers(1, 30))
+        m = np.zeros((H, W), np.uint8)
+        m[rng.integers(H), rng.integers(W)] = 1
+        assert np.array_equal(oracle.danielsson(m)[0], oracle.separable(m)[0])
+    m = np.zeros((1, 9), np.uint8)
+    m[0, 4] = 1
+    D, _ = oracle.danielsson(m)
+    assert D[0, 4] == 0 and (np.delete(D[0], 4) == INF_SQ).all()
+
+
+def test_disconnected_region_is_missed():
+    m = missed_mask()
+    D, R = oracle.danielsson(m)
+    E, F = oracle.separable(m)
+    i, j = MISSED_PIXEL
+    assert D[i, j] > E[i, j]            # the propagation lands on a farther site
+    assert (D >= E).all() and int((D != E).sum()) >= 1

@@ -12,6 +12,7 @@ import oracle
 from tests import test_oracle as T
 from tests import test_oracle_metrics as TM
 from tests import test_oracle_regions as TR
+from tests import test_oracle_danielsson as TD
 
 MUTANTS = [
     ("tie rule reversed", "l_wins_tie = fl < fk;", "l_wins_tie = fl > fk;"),
@@ -74,6 +75,18 @@ MUTANTS = [
      "labels[q] = F[q] < 0 ? -1 : comp[F[q]];", "labels[q] = F[q] < 0 ? -1 : (comp[q] >= 0 ? comp[q] : F[q]);"),
     ("regions search only upwards", "for (int32_t di = -1; di <= 1; ++di) {",
      "for (int32_t di = -1; di <= 0; ++di) {"),
+    ("danielsson takes offers at equal distance", "    if (d[to] > nd) {", "    if (d[to] >= nd) {"),
+    ("danielsson vertical step adds to dx",
+     "for (int32_t j = 0; j < W; ++j) dan_offer(d, y, x, P(i, j), P(i - 1, j), 1, 0);",
+     "for (int32_t j = 0; j < W; ++j) dan_offer(d, y, x, P(i, j), P(i - 1, j), 0, 1);"),
+    ("danielsson first scan starts at the third row", "    for (int32_t i = 1; i < H; ++i) { /* first scan, downwards */",
+     "    for (int32_t i = 2; i < H; ++i) { /* first scan, downwards */"),
+    ("danielsson first scan sweeps the row back left to right",
+     "        for (int32_t j = W - 2; j >= 0; --j) {\n            dan_offer(d, y, x, P(i, j), P(i - 1, j + 1), 1, 1);",
+     "        for (int32_t j = 0; j <= W - 2; ++j) {\n            dan_offer(d, y, x, P(i, j), P(i - 1, j + 1), 1, 1);"),
+    ("danielsson second scan takes the vertical step from above",
+     "for (int32_t j = 0; j < W; ++j) dan_offer(d, y, x, P(i, j), P(i + 1, j), 1, 0);",
+     "for (int32_t j = 0; j < W; ++j) dan_offer(d, y, x, P(i, j), P(i > 0 ? i - 1 : i + 1, j), 1, 0);"),
 ]
 
 
@@ -118,6 +131,12 @@ def _pins():
     yield TR.test_paper_example_components, ()
     for seed in range(4):
         yield TR.test_regions_against_min_propagation, (seed,)
+    yield TD.test_first_scan_matches_figure, ()
+    yield TD.test_final_matches_figure_but_the_erratum, ()
+    for seed in range(3):
+        yield TD.test_never_below_exact_and_consistent, (seed,)
+    yield TD.test_single_sites_exact_and_one_row_propagates_nothing, ()
+    yield TD.test_disconnected_region_is_missed, ()
 
 
 def _failures(lib):
