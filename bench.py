@@ -8,6 +8,8 @@ Workloads (--workload):
   points16k_sq         the same image through edt_sq (distances only);
   disks4k, disks4k_inside, bernoulli256
   disks4k_regions      the disks image through edt_feature and then edt_regions
+  disks1k_danielsson   a 1024^2 disks image through Danielsson's approximate transform,
+                       with its error against the exact one
   disks4k_chamfer      the disks image through edt_sq with the chamfer 4-3 metric,
                        with its error against the exact Euclidean distance
                        other single images (4096^2 disks outside / inside,
@@ -64,6 +66,8 @@ def algo_bytes(kernel: str, H: int, W: int, n: int, with_dist: bool = True) -> i
         return H * W                     # the mask (site slots are a small part)
     if kernel == "k_reg_others":         # mask and F in, labels out
         return H * W * 9
+    if kernel == "k_danielsson":         # mask in; positions written, read back, written; D out
+        return H * W * 21
     if kernel == "k_row_segfill":        # int32 D and F (or D only) out
         return H * W * (8 if with_dist else 4)
     if kernel.startswith("k_row_"):      # int16 rows in, int32 D and F (or D only) out
@@ -103,6 +107,11 @@ SINGLE = {
         desc="4096x4096 uint8 mask, 200 random filled disks (r 5-200) + Bernoulli(1e-4) "
              "points; int32 squared distance + nearest-object index (edt_feature), then the "
              "Voronoi region of every pixel under 8-neighbourhood (edt_regions)"),
+    "disks1k_danielsson": dict(
+        H=1024, W=1024, polarity=0, call="edt_danielsson",
+        desc="1024x1024 uint8 mask, 40 random filled disks (r 5-100) + Bernoulli(1e-4) points; "
+             "Danielsson's approximate squared distances and propagated positions "
+             "(edt_danielsson, one workgroup per image)"),
     "disks4k_chamfer": dict(
         H=4096, W=4096, polarity=0, call="edt_sq", metric=3,
         desc="4096x4096 uint8 mask, 200 random filled disks (r 5-200) + Bernoulli(1e-4) "
@@ -123,6 +132,8 @@ def make_mask(name):
         return workloads.points(16384, 16384, 30)
     if name.startswith("disks4k"):
         return workloads.disks(4096, 4096)
+    if name == "disks1k_danielsson":
+        return workloads.disks(1024, 1024, n_disks=40, rmin=5, rmax=100)
     if name == "bernoulli256":
         return workloads.bernoulli(256, 256, 0.01)
     raise SystemExit(f"unknown workload {name}")
@@ -138,6 +149,7 @@ KERNEL_SOURCES = {
     "k_sqrt": ("edt_api.hip",),
     **{k: ("edt_regions.hip",) for k in ("k_reg_init", "k_reg_union", "k_reg_flatten",
                                          "k_reg_others", "k_reg_sites")},
+    "k_danielsson": ("edt_danielsson.hip",),
 }
 
 
@@ -181,28 +193,32 @@ def cpu_baseline(images, units_px, metric=0):
     for m, pol in images:
         if metric == 3:
             oracle.chamfer_scans(m, pol)
+        elif metric == "danielsson":
+            oracle.danielsson(m, pol)
         else:
             oracle.separable(m, pol, nthreads=threads)
     dt = time.perf_counter() - t0
     what = (f"the whole {images[0][0].shape[0]}x{images[0][0].shape[1]} image" if len(images) == 1
             else f"all {len(images)} images of the batch, one after the other")
     how = ("the oracle's two raster scans of the chamfer 4-3 transform" if metric == 3 else
-           "the oracle's separable transform (vertical pass + lower envelope + fill)")
+           "the oracle's two propagation scans of Danielsson's transform" if metric == "danielsson"
+           else "the oracle's separable transform (vertical pass + lower envelope + fill)")
     return {"value": round(units_px / dt / 1e9, 5), "unit": "Gpixel/s", "cores": threads,
             "kind": "oracle",
             "sample": f"one full pass of {how} over {what}, {threads} thread(s), {dt:.2f} s"}
 
 
-def approx_error(mask, pol, D, ws, stream):
-    """Chamfer 4-3 distance / 3 against the exact Euclidean distance of the
-    same image (computed once by edt_sq, outside the timed region), over the
-    pixels that have a site: mean and largest absolute error in pixels, the
-    range of the relative error, and the share of pixels where they differ."""
+def approx_error(mask, pol, D, ws, stream, scale=3.0, squared=False):
+    """An approximate distance (chamfer 4-3 d / 3, or the square root of
+    Danielsson's d^2) against the exact Euclidean distance of the same image
+    (computed once by edt_sq, outside the timed region), over the pixels that
+    have a site: mean and largest absolute error in pixels, the range of the
+    relative error, and the share of pixels where they differ."""
     import torch
     import paper_2106_03503_amd as edt
     E = edt.sq(mask, polarity=pol, workspace=ws, stream=stream)
     ok = E != edt.EDT_INF_SQ
-    c = D[ok].double() / 3.0
+    c = D[ok].double().sqrt() if squared else D[ok].double() / scale
     e = E[ok].double().sqrt()
     err = c - e
     pos = e > 0
@@ -289,7 +305,12 @@ def run_single(args):
     conn = wl.get("regions", 0)
     L = torch.empty((H, W), dtype=torch.int32, device=dev) if conn else None
 
+    dan = wl.get("call") == "edt_danielsson"
+
     def step():
+        if dan:
+            edt.danielsson(mask, polarity=pol, out_dist=D, out_rel=F, stream=stream)
+            return
         if sq_only:
             edt.sq(mask, polarity=pol, metric=metric, out=D, workspace=ws, stream=stream)
         else:
@@ -302,9 +323,11 @@ def run_single(args):
     px = H * W
     out = base_line(args, px / (ms * 1e-3) / 1e9, ms,
                     {"workload": wl["desc"], "H": H, "W": W, "polarity": pol,
-                     "call": ("edt_sq" if sq_only else "edt_feature")
-                             + (f" + edt_regions ({conn}-neighbourhood)" if conn else ""),
-                     "metric": ["squared Euclidean", "city-block", "chessboard",
+                     "call": "edt_danielsson" if dan else (
+                         ("edt_sq" if sq_only else "edt_feature")
+                         + (f" + edt_regions ({conn}-neighbourhood)" if conn else "")),
+                     "metric": "Danielsson's approximate squared distance" if dan else
+                               ["squared Euclidean", "city-block", "chessboard",
                                 "chamfer 4-3"][metric],
                      "parallelism": "single GPU"})
     out["roofline"] = roofline(kt, lambda k: algo_bytes(k, H, W, n, with_dist=not sq_only),
@@ -316,8 +339,10 @@ def run_single(args):
     out["kernels_ms_per_step"] = {k: round(v[1] / args.steps, 4) for k, v in sorted(kt.items())}
     if metric == 3:
         out["approx_error"] = approx_error(mask, pol, D, ws, stream)
+    if dan:
+        out["approx_error"] = approx_error(mask, pol, D, ws, stream, scale=1.0, squared=True)
     if not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline([(mask_np, pol)], px, metric)
+        out["cpu_baseline"] = cpu_baseline([(mask_np, pol)], px, "danielsson" if dan else metric)
     return out
 
 

@@ -148,6 +148,27 @@ edt_status edt_regions(const uint8_t *mask, int32_t H, int32_t W, int64_t mask_p
                        int32_t polarity, int32_t connectivity, const int32_t *feature,
                        int32_t *labels, int64_t out_pitch, void *stream);
 
+/* Danielsson's APPROXIMATE Euclidean transform (Section 2.3, the two-scan form
+ * given after Grevera), for comparison with the exact one: every pixel holds
+ * the relative position (dy, dx) propagated to it -- the magnitudes of the
+ * offsets to the site it was reached from -- and dist_sq = dy^2 + dx^2, which
+ * is never below the exact value and can exceed it where a site's Voronoi
+ * region is disconnected.  The first scan visits rows 1 .. H-1 and the second
+ * rows H-2 .. 0, so a one-row image propagates nothing.
+ *   mask, H, W, mask_pitch, polarity   as for edt_sq; W <= 8192
+ *   dist_sq     device, int32, H x W, row pitch out_pitch; written
+ *               (EDT_INF_SQ where no position arrived)
+ *   rel         device, int32, H x W, row pitch out_pitch; written:
+ *               (dy << 16) | dx, or -1 where no position arrived; it holds
+ *               the propagation state during the call and may not overlap
+ *               dist_sq (EDT_ERR_INVALID_ARG)
+ * One workgroup runs the two scans in order (the offers are a sequential
+ * chain along each row): this is a comparison kernel, not a fast path.
+ * EDT_ERR_TOO_LARGE for H outside [1, EDT_MAX_SIDE] or W outside [1, 8192]. */
+edt_status edt_danielsson(const uint8_t *mask, int32_t H, int32_t W, int64_t mask_pitch,
+                          int32_t polarity, int32_t *dist_sq, int32_t *rel,
+                          int64_t out_pitch, void *stream);
+
 /* d = sqrt(D) drawn after all squared distances are known (Section 3.1):
  * computed in fp64 and rounded to fp32 (the nearest fp32 to the true root for
  * every D < 2^31); EDT_INF_SQ maps to +infinity.  dist_sq and dist are device

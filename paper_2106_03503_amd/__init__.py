@@ -25,6 +25,7 @@ from ._lib import (  # noqa: F401
     Server,
     EDTError,
     abi_version,
+    danielsson,
     feature,
     library_path,
     profile_begin,

@@ -53,6 +53,8 @@ def _load():
     lib.edt_sqrt_f32.restype = i32
     lib.edt_regions.argtypes = [P, i32, i32, i64, i32, i32, P, P, i64, P]
     lib.edt_regions.restype = i32
+    lib.edt_danielsson.argtypes = [P, i32, i32, i64, i32, P, P, i64, P]
+    lib.edt_danielsson.restype = i32
     lib.edt_profile_begin.argtypes = []
     lib.edt_profile_begin.restype = i32
     lib.edt_profile_end.argtypes = [P, i32, P]
@@ -198,6 +200,22 @@ def regions(mask: torch.Tensor, feature: torch.Tensor, polarity: int = EDT_TO_OB
                             feature.data_ptr(), out.data_ptr(), feature.stride(0),
                             _stream_ptr(stream)), "edt_regions")
     return out
+
+
+def danielsson(mask: torch.Tensor, polarity: int = EDT_TO_OBJECT,
+               out_dist: torch.Tensor | None = None, out_rel: torch.Tensor | None = None,
+               stream=None):
+    """Danielsson's approximate transform (comparison only): (dist_sq, rel)
+    with rel = (dy << 16) | dx the propagated relative position."""
+    mask = _check_mask(mask)
+    H, W = mask.shape
+    D = _check_out(out_dist, H, W, mask.device, "out_dist")
+    R = _check_out(out_rel, H, W, mask.device, "out_rel")
+    if D.stride(0) != R.stride(0):
+        raise ValueError("out_dist and out_rel must share one row pitch")
+    _check(_lib.edt_danielsson(mask.data_ptr(), H, W, mask.stride(0), polarity, D.data_ptr(),
+                               R.data_ptr(), D.stride(0), _stream_ptr(stream)), "edt_danielsson")
+    return D, R
 
 
 def profile_begin() -> None:

@@ -1,0 +1,139 @@
+// Danielsson's approximate Euclidean distance transform (arXiv 2106.03503,
+// Section 2.3, in the two-scan form the paper gives after Grevera): every
+// pixel holds a relative position (dy, dx), the magnitudes of the offsets to
+// the site it was reached from, and d^2 = dy^2 + dx^2.  A reached neighbour
+// offers its position plus one in dy for a vertical step, in dx for a
+// horizontal one and in both for a diagonal one; the pixel takes the offer
+// when it is strictly nearer.  The first scan takes rows 1 .. H-1 downwards
+// (upper neighbour for every pixel; left, upper-left from left to right;
+// upper-right, right from right to left), the second rows H-2 .. 0 upwards
+// (lower neighbour; left, lower-left; right, lower-right).
+//
+// The result depends on the order of the offers pixel by pixel, so a row's
+// sweeps are one sequential chain: one workgroup of one wavefront takes the
+// whole image, the vertical offers and the row transfers on all 64 lanes, the
+// sweeps on lane 0 in LDS.  This is the approximate comparison, not a hot
+// path.  Relative positions travel packed as (dy << 16) | dx, -1 = unreached.
+#include "../../include/edt.h"
+#include "edt_internal.h"
+
+namespace edt {
+namespace {
+
+constexpr int kDanMaxW = 8192;  // two rows of packed positions in LDS
+
+__device__ __forceinline__ int d2_of(int32_t p) {
+    const int dy = p >> 16, dx = p & 0xFFFF;
+    return sqr_c(dy) + sqr_c(dx);
+}
+
+// The pixel holding `cur` takes `from` plus (ay, ax) when strictly nearer.
+__device__ __forceinline__ int32_t offer(int32_t cur, int32_t from, int ay, int ax) {
+    if (from < 0) return cur;
+    const int ny = (from >> 16) + ay, nx = (from & 0xFFFF) + ax;
+    // stored offsets stay within the image, so an offer is at most one past
+    // it; the guard only keeps a 16-bit field from overflowing
+    if (ny > 0x7FFF || nx > 0x7FFF) return cur;
+    const int nd = sqr_c(ny) + sqr_c(nx);
+    if (cur >= 0 && d2_of(cur) <= nd) return cur;
+    return (ny << 16) | nx;
+}
+
+__device__ __forceinline__ int32_t initial(const uint8_t* mask, int64_t mpitch, int pol, int i,
+                                           int j) {
+    const bool obj = mask[(int64_t)i * mpitch + j] != 0;
+    return (pol ? !obj : obj) ? 0 : -1;
+}
+
+__global__ __launch_bounds__(64) void k_danielsson(const uint8_t* mask, int64_t mpitch, int H,
+                                                   int W, int pol, int32_t* dist, int32_t* rel,
+                                                   int64_t opitch) {
+    __shared__ int32_t rowbuf[2][kDanMaxW];
+    const int lane = threadIdx.x;
+    int32_t* prev = rowbuf[0];
+    int32_t* cur = rowbuf[1];
+    auto swap_rows = [&]() {
+        int32_t* t = prev;
+        prev = cur;
+        cur = t;
+    };
+    // row 0 as initialised (the first scan does not visit it)
+    for (int j = lane; j < W; j += 64) {
+        prev[j] = initial(mask, mpitch, pol, 0, j);
+        rel[j] = prev[j];
+    }
+    __syncthreads();
+    for (int i = 1; i < H; ++i) {  // first scan, downwards
+        for (int j = lane; j < W; j += 64)
+            cur[j] = offer(initial(mask, mpitch, pol, i, j), prev[j], 1, 0);
+        __syncthreads();
+        if (lane == 0) {
+            int32_t v = cur[0];
+            for (int j = 1; j < W; ++j) {
+                v = offer(offer(cur[j], v, 0, 1), prev[j - 1], 1, 1);
+                cur[j] = v;
+            }
+            v = cur[W - 1];
+            for (int j = W - 2; j >= 0; --j) {
+                v = offer(offer(cur[j], prev[j + 1], 1, 1), v, 0, 1);
+                cur[j] = v;
+            }
+        }
+        __syncthreads();
+        for (int j = lane; j < W; j += 64) rel[(int64_t)i * opitch + j] = cur[j];
+        swap_rows();
+        __syncthreads();
+    }
+    __threadfence();  // the second scan reads back what the first one wrote
+    // prev holds row H-1 as the first scan left it
+    for (int i = H - 2; i >= 0; --i) {  // second scan, upwards
+        for (int j = lane; j < W; j += 64)
+            cur[j] = offer(rel[(int64_t)i * opitch + j], prev[j], 1, 0);
+        __syncthreads();
+        if (lane == 0) {
+            int32_t v = cur[0];
+            for (int j = 1; j < W; ++j) {
+                v = offer(offer(cur[j], v, 0, 1), prev[j - 1], 1, 1);
+                cur[j] = v;
+            }
+            v = cur[W - 1];
+            for (int j = W - 2; j >= 0; --j) {
+                v = offer(offer(cur[j], v, 0, 1), prev[j + 1], 1, 1);
+                cur[j] = v;
+            }
+        }
+        __syncthreads();
+        for (int j = lane; j < W; j += 64) rel[(int64_t)i * opitch + j] = cur[j];
+        swap_rows();
+        __syncthreads();
+    }
+    __threadfence();
+    for (int i = 0; i < H; ++i)
+        for (int j = lane; j < W; j += 64) {
+            const int32_t p = rel[(int64_t)i * opitch + j];
+            dist[(int64_t)i * opitch + j] = p < 0 ? EDT_INF_SQ : d2_of(p);
+        }
+}
+
+}  // namespace
+}  // namespace edt
+
+extern "C" {
+
+edt_status edt_danielsson(const uint8_t* mask, int32_t H, int32_t W, int64_t mask_pitch,
+                          int32_t polarity, int32_t* dist_sq, int32_t* rel, int64_t out_pitch,
+                          void* stream) {
+    if (H < 1 || W < 1 || H > EDT_MAX_SIDE || W > edt::kDanMaxW) return EDT_ERR_TOO_LARGE;
+    if (!mask || !dist_sq || !rel || mask_pitch < W || out_pitch < W) return EDT_ERR_INVALID_ARG;
+    if (polarity != EDT_TO_OBJECT && polarity != EDT_TO_BACKGROUND) return EDT_ERR_INVALID_ARG;
+    const uintptr_t d0 = reinterpret_cast<uintptr_t>(dist_sq);
+    const uintptr_t r0 = reinterpret_cast<uintptr_t>(rel);
+    const uintptr_t span = 4 * (uintptr_t)((H - 1) * out_pitch + W);
+    if (d0 < r0 + span && r0 < d0 + span) return EDT_ERR_INVALID_ARG;  // rel is read back
+    EDT_LAUNCH_AS("k_danielsson", edt::k_danielsson, dim3(1), dim3(64), 0,
+                  reinterpret_cast<hipStream_t>(stream), mask, mask_pitch, H, W, polarity,
+                  dist_sq, rel, out_pitch);
+    return hipGetLastError() == hipSuccess ? EDT_OK : EDT_ERR_DEVICE;
+}
+
+}  // extern "C"

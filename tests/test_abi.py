@@ -95,6 +95,15 @@ def test_argument_validation_returns_before_any_launch(edt):
     assert lib.edt_regions(fake, 10, 10, 10, 0, 6, fake, big, 10, None) == -1
     assert lib.edt_regions(fake, 10, 10, 10, 0, 8, big + 40, big, 10, None) == -1  # labels over feature
     assert lib.edt_regions(big + 4, 10, 10, 10, 0, 8, fake, big, 10, None) == -1   # labels over mask
+    # Danielsson: sizes, pointers, pitches, polarity, dist over rel
+    assert lib.edt_danielsson(fake, 10, 8193, 8193, 0, big, big + 400000, 8193, None) == -3
+    assert lib.edt_danielsson(fake, 0, 10, 10, 0, big, big + 4000, 10, None) == -3
+    assert lib.edt_danielsson(None, 10, 10, 10, 0, big, big + 4000, 10, None) == -1
+    assert lib.edt_danielsson(fake, 10, 10, 10, 0, None, big + 4000, 10, None) == -1
+    assert lib.edt_danielsson(fake, 10, 10, 10, 0, big, None, 10, None) == -1
+    assert lib.edt_danielsson(fake, 10, 10, 9, 0, big, big + 4000, 10, None) == -1
+    assert lib.edt_danielsson(fake, 10, 10, 10, 3, big, big + 4000, 10, None) == -1
+    assert lib.edt_danielsson(fake, 10, 10, 10, 0, big, big + 40, 10, None) == -1  # overlap
     # sqrt
     assert lib.edt_sqrt_f32(fake, fake, -1, None) == -1
     assert lib.edt_sqrt_f32(None, fake, 5, None) == -1
