@@ -164,7 +164,9 @@ edt_status edt_regions(const uint8_t *mask, int32_t H, int32_t W, int64_t mask_p
  *               dist_sq (EDT_ERR_INVALID_ARG)
  * One workgroup runs the two scans in order (the offers are a sequential
  * chain along each row): this is a comparison kernel, not a fast path.
- * EDT_ERR_TOO_LARGE for H outside [1, EDT_MAX_SIDE] or W outside [1, 8192]. */
+ * EDT_ERR_TOO_LARGE for H outside [1, EDT_MAX_SIDE], W outside [1, 8192] or
+ * more than 2^22 pixels (the sequential chain takes about 0.8 s per million
+ * pixels). */
 edt_status edt_danielsson(const uint8_t *mask, int32_t H, int32_t W, int64_t mask_pitch,
                           int32_t polarity, int32_t *dist_sq, int32_t *rel,
                           int64_t out_pitch, void *stream);

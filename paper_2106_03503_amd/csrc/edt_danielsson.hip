@@ -21,6 +21,9 @@ namespace edt {
 namespace {
 
 constexpr int kDanMaxW = 8192;  // two rows of packed positions in LDS
+// The offers are one chain of about 4 H W steps on one lane (about 0.8 us per
+// thousand pixels): images are capped so that a call stays within seconds.
+constexpr int64_t kDanMaxPixels = (int64_t)1 << 22;
 
 __device__ __forceinline__ int d2_of(int32_t p) {
     const int dy = p >> 16, dx = p & 0xFFFF;
@@ -123,7 +126,9 @@ extern "C" {
 edt_status edt_danielsson(const uint8_t* mask, int32_t H, int32_t W, int64_t mask_pitch,
                           int32_t polarity, int32_t* dist_sq, int32_t* rel, int64_t out_pitch,
                           void* stream) {
-    if (H < 1 || W < 1 || H > EDT_MAX_SIDE || W > edt::kDanMaxW) return EDT_ERR_TOO_LARGE;
+    if (H < 1 || W < 1 || H > EDT_MAX_SIDE || W > edt::kDanMaxW ||
+        (int64_t)H * W > edt::kDanMaxPixels)
+        return EDT_ERR_TOO_LARGE;
     if (!mask || !dist_sq || !rel || mask_pitch < W || out_pitch < W) return EDT_ERR_INVALID_ARG;
     if (polarity != EDT_TO_OBJECT && polarity != EDT_TO_BACKGROUND) return EDT_ERR_INVALID_ARG;
     const uintptr_t d0 = reinterpret_cast<uintptr_t>(dist_sq);

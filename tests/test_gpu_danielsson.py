@@ -72,6 +72,7 @@ def test_missed_region(edt):
 
 def test_errors(edt):
     import torch
-    with pytest.raises(edt.EDTError) as e:
-        edt.danielsson(torch.zeros((4, 8193), dtype=torch.uint8, device="cuda:0"))
-    assert e.value.status == -3
+    for shape in ((4, 8193), (1025, 4096)):
+        with pytest.raises(edt.EDTError) as e:
+            edt.danielsson(torch.zeros(shape, dtype=torch.uint8, device="cuda:0"))
+        assert e.value.status == -3
