@@ -44,6 +44,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "Gpixel/s exact sq-EDT+feature transform and % HBM roofline; batched vs per-image"
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published peak
+SWEEP_RATES = (100.0, 250.0, 500.0, 1000.0, 2000.0, 5000.0)
 PATH_BYTES_PER_PX = 13.0  # 1 mask + 2 + 2 intermediate + 4 D + 4 F
 
 
@@ -443,11 +444,11 @@ def run_serve(args):
     budget = int(args.budget_gib * (1 << 30))
     stream = torch.cuda.current_stream()
 
-    def replay(srv):
+    def replay(srv, scale=1.0):
         t0 = time.perf_counter()
         tickets = []
         for r, m, (D, F) in zip(reqs, masks, outs):
-            while time.perf_counter() - t0 < r["t"]:
+            while time.perf_counter() - t0 < r["t"] * scale:
                 pass
             while True:
                 try:
@@ -493,6 +494,20 @@ def run_serve(args):
                     "replay_ms": [round(w * 1e3, 2) for w in walls]}
     out["path_hbm"] = {"bytes_per_px": round(bytes_path / px, 3), "achieved_GBs": round(gbs, 1),
                        "frac": round(gbs / HBM_PEAK_GBS, 4)}
+    if args.sweep and not burst:
+        # the same requests at other rates: the arrival times scale with 1/rate
+        sweep = []
+        for rate in SWEEP_RATES:
+            with edt.Server(budget, n_streams=args.streams) as srv:
+                w, st_r = replay(srv, args.rate / rate)
+            sweep.append({"rate_per_s": rate,
+                          "offered_gpix_per_s": round(px / (reqs[-1]["t"] * args.rate / rate) / 1e9, 3),
+                          "gpix_per_s": round(st_r["gpix_per_s"], 3),
+                          "p50_ms": round(st_r["p50_ns"] / 1e6, 3),
+                          "p99_ms": round(st_r["p99_ns"] / 1e6, 3),
+                          "launches": st_r["launches"]})
+            print(f"serve: sweep {rate:g}/s {w * 1e3:.1f} ms", file=sys.stderr, flush=True)
+        out["serve"]["sweep"] = sweep
     if not args.no_cpu:
         # a bounded sample: the requests in arrival order up to ~1e8 pixels
         sample, acc = [], 0
@@ -520,6 +535,8 @@ def main():
     ap.add_argument("--requests", type=int, default=400, help="serve: requests per replay")
     ap.add_argument("--budget-gib", type=float, default=16.0, help="serve: memory budget")
     ap.add_argument("--streams", type=int, default=4, help="serve: server streams")
+    ap.add_argument("--sweep", action="store_true",
+                    help="serve: also replay the same requests at 100..5000 req/s")
     ap.add_argument("--no-cpu", action="store_true", help="skip the cpu_baseline leg")
     ap.add_argument("--no-per-image", action="store_true",
                     help="batch2048: skip the per-image edt_feature leg")
