@@ -107,6 +107,14 @@ __device__ __forceinline__ void bits_item(const Img& g, const Views& v, int item
 // b (the downward sweep's state entering band b), down[b][c] the first site
 // row in the bands below b (the upward sweep's state); flag[c] tells whether
 // column c holds any site (zero past W up to the list capacity).
+// With kCache (single images) a thread whose slice has at most kCarryPer bands
+// reads their masks once, into registers, for the slice's summary and both
+// sweeps; otherwise (batches, whose images are mostly one band per slice, and
+// images taller than kCarryPer * kCarrySlices bands) it reads them again for
+// each sweep, with fewer registers.
+constexpr int kCarryPer = 16;
+
+template <bool kCache>
 __device__ void carry_item(const Img& g, const Views& v, int bx) {
     __shared__ int s_last[kCarrySlices][kCarryCols];
     __shared__ int s_first[kCarrySlices][kCarryCols];
@@ -117,6 +125,47 @@ __device__ void carry_item(const Img& g, const Views& v, int bx) {
     const int c = bx * kCarryCols + lane;
     const int b0 = (int)((int64_t)nb * s / kCarrySlices);
     const int b1 = (int)((int64_t)nb * (s + 1) / kCarrySlices);
+    if (kCache && nb <= kCarryPer * kCarrySlices) {  // uniform: every slice fits
+        const int cnt = b1 - b0;
+        uint64_t m[kCarryPer];
+#pragma unroll
+        for (int k = 0; k < kCarryPer; ++k) {
+            m[k] = 0;
+            if (k < cnt && c < W) m[k] = v.bits[(int64_t)(b0 + k) * W + c];
+        }
+        int last = -1, first = kNoBelow;
+#pragma unroll
+        for (int k = 0; k < kCarryPer; ++k) {
+            if (m[k]) {  // zero past the slice
+                if (first == kNoBelow) first = (b0 + k) * kBand + __builtin_ctzll(m[k]);
+                last = (b0 + k) * kBand + 63 - __builtin_clzll(m[k]);
+            }
+        }
+        s_last[s][lane] = last;
+        s_first[s][lane] = first;
+        __syncthreads();
+        int run = -1;
+        for (int q = 0; q < s; ++q) run = max(run, s_last[q][lane]);
+        int run_dn = kNoBelow;
+        for (int q = kCarrySlices - 1; q > s; --q) run_dn = min(run_dn, s_first[q][lane]);
+        __syncthreads();  // s_last / s_first are reused by the next item
+        if (c >= W) {
+            if (s == 0 && c < cand_pitch(W)) v.flag[c] = 0;
+            return;
+        }
+#pragma unroll
+        for (int k = 0; k < kCarryPer; ++k) {
+            if (k < cnt) v.up[(int64_t)(b0 + k) * W + c] = (int16_t)run;
+            if (m[k]) run = (b0 + k) * kBand + 63 - __builtin_clzll(m[k]);
+        }
+        if (s == kCarrySlices - 1) v.flag[c] = run >= 0;
+#pragma unroll
+        for (int k = kCarryPer - 1; k >= 0; --k) {
+            if (k < cnt) v.down[(int64_t)(b0 + k) * W + c] = (int16_t)run_dn;
+            if (m[k]) run_dn = (b0 + k) * kBand + __builtin_ctzll(m[k]);
+        }
+        return;
+    }
     int last = -1, first = kNoBelow;
     if (c < W) {
         for (int b = b0; b < b1; ++b) {
@@ -264,7 +313,7 @@ __global__ __launch_bounds__(64 * kColWaves) void k_bits(Img g, int items) {
 }
 __global__ __launch_bounds__(kCarryCols* kCarrySlices) void k_carry(Img g) {
     const Views v = views_of(g);
-    carry_item(g, v, blockIdx.x);
+    carry_item<true>(g, v, blockIdx.x);
 }
 __global__ __launch_bounds__(1024) void k_compact(Img g) {
     const Views v = views_of(g);
@@ -307,7 +356,7 @@ __global__ __launch_bounds__(kCarryCols* kCarrySlices) void k_carry_batch(BatchT
     for (int item = blockIdx.x; item < total; item += gridDim.x) {
         const int im = batch_lookup<kPhCarry>(t, item);
         const Img g = batch_img(t, im);
-        carry_item(g, views_of(g), item - t.prefix[kPhCarry][im]);
+        carry_item<false>(g, views_of(g), item - t.prefix[kPhCarry][im]);
     }
 }
 __global__ __launch_bounds__(1024) void k_compact_batch(BatchTable t, int total) {
