@@ -27,7 +27,8 @@ Workloads (--workload):
                        throughput and p50/p99 latency (submission to observed
                        completion).
 Inputs are resident in HBM before the timed region.  Prints ONE JSON line.
---gpus N > 1 is refused: this build runs on one GPU.
+--gpus N > 1 is refused: the library has no multi-GPU path, so the benchmark runs
+on one GPU.
 """
 from __future__ import annotations
 
@@ -559,7 +560,7 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported.",
+        print(f"bench.py: the library runs on one GPU; --gpus {args.gpus} is not supported.",
               file=sys.stderr)
         sys.exit(2)
     if args.copy_calibration:

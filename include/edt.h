@@ -88,7 +88,7 @@ int32_t edt_abi_version(void);
 const char *edt_status_string(edt_status s);
 
 /* Bytes of device workspace that edt_sq / edt_feature need for an H x W image
- * (want_feature does not change the size in this build).  Returns 0 when H or
+ * (the size does not depend on want_feature at present).  Returns 0 when H or
  * W is outside [1, EDT_MAX_SIDE]. */
 size_t edt_workspace_bytes(int32_t H, int32_t W, int32_t want_feature);
 
