@@ -31,7 +31,7 @@ int32_t pack_table(const BatchImage* img, int n, int lane_w, uint8_t* dst, int* 
     int mw = 0;
     for (int q = 0; q < n; ++q) {
         const int H = img[q].H, W = img[q].W;
-        const bool lanes = W <= lane_w;
+        const bool lanes = W <= lane_w && H <= kLanePackMaxH;
         const int64_t items[kPhases] = {items_bits(H, W), items_carry(H, W), 1, items_near(H, W),
                                         lanes ? 0 : H, lanes ? items_lanes(H) : 0};
         for (int p = 0; p < kPhases; ++p) {

@@ -145,6 +145,9 @@ __host__ __device__ inline int items_near(int H, int W) {
 constexpr int kLaneRows = 64;
 constexpr int kLaneRing = 16;
 constexpr int kLaneMaxW = 1024;
+// Tallest image the one-lane-per-row pass takes (its stack entries pack the
+// site row into 12 bits).
+constexpr int kLanePackMaxH = 4096;
 __host__ __device__ inline int items_lanes(int H) { return (H + kLaneRows - 1) / kLaneRows; }
 
 // Phases of the transform, in launch order (a batch image's rows are work

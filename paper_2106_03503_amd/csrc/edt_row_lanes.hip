@@ -31,16 +31,38 @@ static_assert((R & (R - 1)) == 0, "ring slots are taken modulo R with a mask");
 static_assert(RB % 8 == 0, "blocks are whole 16-byte pieces of starts");
 constexpr int kBlk = 32;  // candidates per load of site rows (64 bytes per lane)
 
-// LDS of one wavefront: the scan keeps the top R stack entries of every lane
-// here; the fill then reuses the space for one row's whole envelope.
+// Stack entries.  Unpacked (the segment scan of single images, W up to
+// 16384): the candidate (column << 16 | site row) in a 32-bit word and its
+// start (first pixel it owns) in an int16 beside it.  Packed (batch images,
+// W <= kLaneMaxW and H <= kLanePackMaxH): column, start and site row in one
+// word, so that an entry moves as 4 bytes instead of 6 and the ring as one
+// array.
+__device__ __forceinline__ uint32_t pk_entry(int col, int start, int row) {
+    return ((uint32_t)col << 22) | ((uint32_t)start << 12) | (uint32_t)row;
+}
+__device__ __forceinline__ int pk_col(uint32_t c) { return (int)(c >> 22); }
+__device__ __forceinline__ int pk_start(uint32_t c) { return (int)((c >> 12) & 0x3FFu); }
+__device__ __forceinline__ int pk_row(uint32_t c) { return (int)(c & 0xFFFu); }
+static_assert(kLaneMaxW <= 1024 && kLanePackMaxH <= 4096,
+              "ten bits of column, ten of start (below W), twelve of site row");
+
+// LDS of one wavefront's scan: the top R stack entries of every lane.
+template <bool kPk>
+struct LaneRing {
+    uint32_t c[R][kLaneRows];  // packed candidate (column << 16 | site row)
+    int16_t s[R][kLaneRows];   // first pixel it owns
+};
+template <>
+struct LaneRing<true> {
+    uint32_t c[R][kLaneRows];  // packed entry
+};
+
+// LDS of the batch kernel: the ring while scanning, then one row's whole
+// envelope (packed entries) while filling.
 union LaneLds {
-    struct {
-        uint32_t c[R][kLaneRows];  // packed candidate (column << 16 | site row)
-        int16_t s[R][kLaneRows];   // first pixel it owns
-    } ring;
+    LaneRing<true> ring;
     struct {
         uint32_t c[kLaneMaxW];
-        int16_t s[kLaneMaxW];
     } row;
 };
 
@@ -59,12 +81,13 @@ __device__ __forceinline__ void put4(int32_t* __restrict__ p, int j, int W, bool
     }
 }
 
-// Last index e in [lo, hi) with st[e] <= j, given st[lo] <= j.
-__device__ __forceinline__ int last_at_or_before(const int16_t* st, int lo, int hi, int j) {
+// Last index e in [lo, hi) whose packed entry starts at or before j, given
+// that entry lo does.
+__device__ __forceinline__ int last_at_or_before(const uint32_t* c, int lo, int hi, int j) {
     int a = lo, b = hi - 1;
     while (a < b) {
         const int mid = (a + b + 1) >> 1;
-        if (st[mid] <= j)
+        if (pk_start(c[mid]) <= j)
             a = mid;
         else
             b = mid - 1;
@@ -72,18 +95,14 @@ __device__ __forceinline__ int last_at_or_before(const int16_t* st, int lo, int 
     return a;
 }
 
-// Move ring block [b, b + RB) of this lane to memory (ranks b.. of (sc, rr));
-// b is a multiple of RB.
+// Move ring block [b, b + RB) of this lane to memory (ranks b.. of sc, and of
+// rr for the unpacked starts); b is a multiple of RB.
+template <bool kPk>
 __device__ __forceinline__ void spill_block(int b, uint32_t* sc, int16_t* rr, bool vec,
-                                            LaneLds& sh, int lane) {
+                                            LaneRing<kPk>& ring, int lane) {
     uint32_t c[RB];
-    uint32_t sp[RB / 2];
 #pragma unroll
-    for (int k = 0; k < RB; ++k) c[k] = sh.ring.c[(b + k) & (R - 1)][lane];
-#pragma unroll
-    for (int k = 0; k < RB / 2; ++k)
-        sp[k] = (uint32_t)(uint16_t)sh.ring.s[(b + 2 * k) & (R - 1)][lane] |
-                ((uint32_t)(uint16_t)sh.ring.s[(b + 2 * k + 1) & (R - 1)][lane] << 16);
+    for (int k = 0; k < RB; ++k) c[k] = ring.c[(b + k) & (R - 1)][lane];
     if (vec) {
 #pragma unroll
         for (int k = 0; k < RB / 4; ++k)
@@ -93,15 +112,23 @@ __device__ __forceinline__ void spill_block(int b, uint32_t* sc, int16_t* rr, bo
 #pragma unroll
         for (int k = 0; k < RB; ++k) sc[b + k] = c[k];
     }
+    if constexpr (!kPk) {
+        uint32_t sp[RB / 2];
 #pragma unroll
-    for (int k = 0; k < RB / 8; ++k)
-        *reinterpret_cast<int4*>(rr + b + 8 * k) =
-            make_int4((int)sp[4 * k], (int)sp[4 * k + 1], (int)sp[4 * k + 2], (int)sp[4 * k + 3]);
+        for (int k = 0; k < RB / 2; ++k)
+            sp[k] = (uint32_t)(uint16_t)ring.s[(b + 2 * k) & (R - 1)][lane] |
+                    ((uint32_t)(uint16_t)ring.s[(b + 2 * k + 1) & (R - 1)][lane] << 16);
+#pragma unroll
+        for (int k = 0; k < RB / 8; ++k)
+            *reinterpret_cast<int4*>(rr + b + 8 * k) =
+                make_int4((int)sp[4 * k], (int)sp[4 * k + 1], (int)sp[4 * k + 2], (int)sp[4 * k + 3]);
+    }
 }
 
 // Bring block [b, b + RB) of this lane back from memory into the ring.
+template <bool kPk>
 __device__ __forceinline__ void fill_block(int b, const uint32_t* sc, const int16_t* rr, bool vec,
-                                           LaneLds& sh, int lane) {
+                                           LaneRing<kPk>& ring, int lane) {
     uint32_t c[RB];
     if (vec) {
 #pragma unroll
@@ -116,19 +143,21 @@ __device__ __forceinline__ void fill_block(int b, const uint32_t* sc, const int1
 #pragma unroll
         for (int k = 0; k < RB; ++k) c[k] = sc[b + k];
     }
-    uint32_t sp[RB / 2];
 #pragma unroll
-    for (int k = 0; k < RB / 8; ++k) {
-        const int4 x = *reinterpret_cast<const int4*>(rr + b + 8 * k);
-        sp[4 * k] = (uint32_t)x.x;
-        sp[4 * k + 1] = (uint32_t)x.y;
-        sp[4 * k + 2] = (uint32_t)x.z;
-        sp[4 * k + 3] = (uint32_t)x.w;
-    }
+    for (int k = 0; k < RB; ++k) ring.c[(b + k) & (R - 1)][lane] = c[k];
+    if constexpr (!kPk) {
+        uint32_t sp[RB / 2];
 #pragma unroll
-    for (int k = 0; k < RB; ++k) {
-        sh.ring.c[(b + k) & (R - 1)][lane] = c[k];
-        sh.ring.s[(b + k) & (R - 1)][lane] = (int16_t)(sp[k >> 1] >> (16 * (k & 1)));
+        for (int k = 0; k < RB / 8; ++k) {
+            const int4 x = *reinterpret_cast<const int4*>(rr + b + 8 * k);
+            sp[4 * k] = (uint32_t)x.x;
+            sp[4 * k + 1] = (uint32_t)x.y;
+            sp[4 * k + 2] = (uint32_t)x.z;
+            sp[4 * k + 3] = (uint32_t)x.w;
+        }
+#pragma unroll
+        for (int k = 0; k < RB; ++k)
+            ring.s[(b + k) & (R - 1)][lane] = (int16_t)(sp[k >> 1] >> (16 * (k & 1)));
     }
 }
 
@@ -139,9 +168,10 @@ __device__ __forceinline__ void fill_block(int b, const uint32_t* sc, const int1
 // piece, and a pop below the ring brings a block back, so the loop touches
 // memory in whole 64- and 32-byte pieces and waits for it only when it reads
 // the next 32 site rows or, rarely, brings a block back.
+template <bool kPk>
 __device__ __forceinline__ int scan_row(const int i, const int n, const int W,
                                         const int16_t* __restrict__ cols, int16_t* rr,
-                                        uint32_t* sc, const bool vec, LaneLds& sh,
+                                        uint32_t* sc, const bool vec, LaneRing<kPk>& ring,
                                         const int lane) {
     int M = 0, base = 0;
     int colA = 0, rowA = 0, gA = 0, sA = 0;  // top entry (M - 1)
@@ -179,10 +209,16 @@ __device__ __forceinline__ int scan_row(const int i, const int n, const int W,
                     if (!(dC < dAs || (dC == dAs && row < rowA))) break;
                     --M;
                     if (M > 0) {
-                        colA = (int)(cB >> 16);
-                        rowA = (int)(cB & 0xFFFFu);
+                        if constexpr (kPk) {
+                            colA = pk_col(cB);
+                            rowA = pk_row(cB);
+                            sA = pk_start(cB);
+                        } else {
+                            colA = (int)(cB >> 16);
+                            rowA = (int)(cB & 0xFFFFu);
+                            sA = sB;
+                        }
                         gA = sqr_c(i - rowA);
-                        sA = sB;
                         dAs = gA + sqr_c(sA - colA);
                         dAe = gA + sqr_c(W - 1 - colA);
                     }
@@ -190,10 +226,10 @@ __device__ __forceinline__ int scan_row(const int i, const int n, const int W,
                         const int e = M - 2;
                         if (e < base) {  // below the ring: bring its block back
                             base -= RB;
-                            fill_block(base, sc, rr, vec, sh, lane);
+                            fill_block<kPk>(base, sc, rr, vec, ring, lane);
                         }
-                        cB = sh.ring.c[e & (R - 1)][lane];
-                        sB = sh.ring.s[e & (R - 1)][lane];
+                        cB = ring.c[e & (R - 1)][lane];
+                        if constexpr (!kPk) sB = ring.s[e & (R - 1)][lane];
                     }
                 }
                 int s = 0;
@@ -201,15 +237,23 @@ __device__ __forceinline__ int scan_row(const int i, const int n, const int W,
                     if (!(dCe < dAe || (dCe == dAe && row < rowA))) continue;  // never wins in the row
                     s = first_after(gC - gA + mul_c(col - colA, col + colA) - (row < rowA ? 1 : 0),
                                     2 * (col - colA), W);
-                    cB = ((uint32_t)colA << 16) | (uint32_t)rowA;
-                    sB = sA;
+                    if constexpr (kPk) {
+                        cB = pk_entry(colA, sA, rowA);
+                    } else {
+                        cB = ((uint32_t)colA << 16) | (uint32_t)rowA;
+                        sB = sA;
+                    }
                 }
                 if (M - base == R) {  // ring full: its older block goes to memory
-                    spill_block(base, sc, rr, vec, sh, lane);
+                    spill_block<kPk>(base, sc, rr, vec, ring, lane);
                     base += RB;
                 }
-                sh.ring.c[M & (R - 1)][lane] = ((uint32_t)col << 16) | (uint32_t)row;
-                sh.ring.s[M & (R - 1)][lane] = (int16_t)s;
+                if constexpr (kPk) {
+                    ring.c[M & (R - 1)][lane] = pk_entry(col, s, row);
+                } else {
+                    ring.c[M & (R - 1)][lane] = ((uint32_t)col << 16) | (uint32_t)row;
+                    ring.s[M & (R - 1)][lane] = (int16_t)s;
+                }
                 colA = col;
                 rowA = row;
                 gA = gC;
@@ -221,8 +265,8 @@ __device__ __forceinline__ int scan_row(const int i, const int n, const int W,
         }
     }
     for (int e = base; e < M; ++e) {  // the rest of the stack to memory
-        sc[e] = sh.ring.c[e & (R - 1)][lane];
-        rr[e] = sh.ring.s[e & (R - 1)][lane];
+        sc[e] = ring.c[e & (R - 1)][lane];
+        if constexpr (!kPk) rr[e] = ring.s[e & (R - 1)][lane];
     }
     return M;
 }
@@ -249,27 +293,22 @@ __global__ __launch_bounds__(kLaneRows) void k_row_lanes_batch(BatchTable tb) {
                      (g.opitch % 4 == 0);
     if (n > 0 && lane < rows) {
         const int i = i0 + lane;
-        s_m[lane] = scan_row(i, n, W, v.cols, v.rc + (int64_t)i * pitch,
-                             reinterpret_cast<uint32_t*>(base + (int64_t)i * g.opitch), vec, sh,
-                             lane);
+        s_m[lane] = scan_row<true>(i, n, W, v.cols, v.rc + (int64_t)i * pitch,
+                                   reinterpret_cast<uint32_t*>(base + (int64_t)i * g.opitch), vec,
+                                   sh.ring, lane);
     }
     __syncthreads();  // stacks in memory are complete; the ring is free
 
     // the envelope of row r + 1 is in flight while row r is filled
     constexpr int kPer = kLaneMaxW / kLaneRows;  // entries per lane
     uint32_t pc[kPer];
-    int16_t ps[kPer];
     auto fetch = [&](int r) {
         const int Mr = n > 0 ? s_m[r] : 0;
         const uint32_t* sc = reinterpret_cast<const uint32_t*>(base + (int64_t)(i0 + r) * g.opitch);
-        const int16_t* rr = v.rc + (int64_t)(i0 + r) * pitch;
 #pragma unroll
         for (int k = 0; k < kPer; ++k) {
             const int e = lane + k * kLaneRows;
-            if (e < Mr) {
-                pc[k] = sc[e];
-                ps[k] = rr[e];
-            }
+            if (e < Mr) pc[k] = sc[e];
         }
     };
     if (rows > 0) fetch(0);
@@ -281,10 +320,7 @@ __global__ __launch_bounds__(kLaneRows) void k_row_lanes_batch(BatchTable tb) {
 #pragma unroll
         for (int k = 0; k < kPer; ++k) {
             const int e = lane + k * kLaneRows;
-            if (e < M) {
-                sh.row.c[e] = pc[k];
-                sh.row.s[e] = ps[k];
-            }
+            if (e < M) sh.row.c[e] = pc[k];
         }
         __syncthreads();
         if (r + 1 < rows) fetch(r + 1);
@@ -301,13 +337,13 @@ __global__ __launch_bounds__(kLaneRows) void k_row_lanes_batch(BatchTable tb) {
                 // owner of pixel j: the last entry starting at or before it,
                 // searched from this lane's previous owner
                 int step = 1;
-                while (e + step < M && sh.row.s[e + step] <= j) {
+                while (e + step < M && pk_start(sh.row.c[e + step]) <= j) {
                     e += step;
                     step <<= 1;
                 }
-                e = last_at_or_before(sh.row.s, e, min(M, e + step), j);
+                e = last_at_or_before(sh.row.c, e, min(M, e + step), j);
                 uint32_t c = sh.row.c[e];
-                int nst = e + 1 < M ? sh.row.s[e + 1] : INT32_MAX;
+                int nst = e + 1 < M ? pk_start(sh.row.c[e + 1]) : INT32_MAX;
 #pragma unroll
                 for (int q = 0; q < 4; ++q) {
                     const int jj = j + q;
@@ -317,9 +353,9 @@ __global__ __launch_bounds__(kLaneRows) void k_row_lanes_batch(BatchTable tb) {
                         while (jj >= nst) {
                             ++e;
                             c = sh.row.c[e];
-                            nst = e + 1 < M ? sh.row.s[e + 1] : INT32_MAX;
+                            nst = e + 1 < M ? pk_start(sh.row.c[e + 1]) : INT32_MAX;
                         }
-                        const int col = (int)(c >> 16), row = (int)(c & 0xFFFFu);
+                        const int col = pk_col(c), row = pk_row(c);
                         d[q] = sqr_c(i - row) + sqr_c(jj - col);
                         f[q] = mul_c(row, W) + col;
                     }
@@ -340,7 +376,7 @@ __global__ __launch_bounds__(kLaneRows) void k_row_lanes_batch(BatchTable tb) {
 // kSparseMaxN of them are left to the one-wavefront row pass.
 template <int L>
 __global__ __launch_bounds__(kLaneRows) void k_row_segscan(Img g, int16_t* __restrict__ segm) {
-    __shared__ LaneLds sh;
+    __shared__ LaneRing<false> ring;
     const Views v = views_of(g);
     const int n = v.meta[0];
     if (n <= kSparseMaxN) return;
@@ -358,8 +394,8 @@ __global__ __launch_bounds__(kLaneRows) void k_row_segscan(Img g, int16_t* __res
         const int i = grp * kLaneRows + lane;
         if (i < g.H) {
             uint32_t* sc = reinterpret_cast<uint32_t*>(base + (int64_t)i * g.opitch) + q0;
-            const int M = scan_row(i, min(L, n - q0), g.W, v.cols + q0,
-                                   v.rc + (int64_t)i * pitch + q0, sc, vec, sh, lane);
+            const int M = scan_row<false>(i, min(L, n - q0), g.W, v.cols + q0,
+                                          v.rc + (int64_t)i * pitch + q0, sc, vec, ring, lane);
             segm[(int64_t)i * seg_count(g.W) + y * (L / kSegL)] = (int16_t)M;
         }
     }

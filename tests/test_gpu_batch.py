@@ -114,7 +114,7 @@ def _deep_pop_mask(H, W, seed):
     """Rows whose envelopes grow long and are then mostly popped at once: in
     each row band the site rows drift away slowly from left to right (every
     parabola survives), then a column with a site in the band itself hides
-    dozens of them, more than the 32 stack entries a lane keeps in LDS."""
+    dozens of them, more than the 16 stack entries a lane keeps in LDS."""
     rng = np.random.default_rng(seed)
     m = np.zeros((H, W), np.uint8)
     for c in range(W):
@@ -140,6 +140,23 @@ def test_lane_rows_deep_pops_and_ties(edt):
         imgs.append((1 - m, 1, True))
     for (H, W) in [(1, 1), (1, 4096), (4096, 1), (3, 5), (64, 64)]:
         imgs.append(((rng.random((H, W)) < 0.3).astype(np.uint8), 0, True))
+    _check_batch(edt, imgs, submits=2)
+
+
+def test_lane_rows_at_the_packed_height_limit(edt):
+    """The one-lane-per-row pass packs a stack entry's site row into 12 bits:
+    images 4096 rows tall take it with sites on their last row (row 4095) and
+    deep stacks; one row taller goes to the one-workgroup-per-row pass.  Both
+    polarities, against the oracle."""
+    rng = np.random.default_rng(12)
+    imgs = []
+    for H in (4096, 4097):
+        m = np.zeros((H, 300), np.uint8)
+        m[H - 1, ::7] = 1                                   # sites on the last row
+        m[rng.integers(0, H, 40), rng.integers(0, 300, 40)] = 1
+        m[(np.arange(300) * 13) % H, np.arange(300)] = 1    # a site in every column
+        imgs.append((m, 0, True))
+        imgs.append((m, 1, True))
     _check_batch(edt, imgs, submits=2)
 
 
