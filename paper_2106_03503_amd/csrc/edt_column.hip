@@ -103,7 +103,8 @@ __device__ __forceinline__ void bits_item(const Img& g, const Views& v, int item
 
 // --------------------------------------------------------------- carry
 // Work item bx: kCarryCols columns; each of the kCarrySlices wavefronts owns a
-// contiguous slice of bands.  up[b][c] is the last site row in the bands above
+// contiguous slice of bands (images of at most kCarrySmallBands bands: one
+// thread per column and no slices, kCarryCols * kCarrySlices columns).  up[b][c] is the last site row in the bands above
 // b (the downward sweep's state entering band b), down[b][c] the first site
 // row in the bands below b (the upward sweep's state); flag[c] tells whether
 // column c holds any site (zero past W up to the list capacity).
@@ -120,6 +121,31 @@ __device__ void carry_item(const Img& g, const Views& v, int bx) {
     __shared__ int s_first[kCarrySlices][kCarryCols];
     const int nb = (g.H + kBand - 1) / kBand;
     const int W = g.W;
+    if (nb <= kCarrySmallBands) {  // uniform: one thread per column, all bands
+        const int c = bx * (kCarryCols * kCarrySlices) + (int)threadIdx.x;
+        if (c >= W) {
+            if (c < cand_pitch(W)) v.flag[c] = 0;
+            return;
+        }
+        uint64_t m[kCarrySmallBands];
+#pragma unroll
+        for (int b = 0; b < kCarrySmallBands; ++b)
+            m[b] = b < nb ? v.bits[(int64_t)b * W + c] : 0ull;
+        int run = -1;
+#pragma unroll
+        for (int b = 0; b < kCarrySmallBands; ++b) {
+            if (b < nb) v.up[(int64_t)b * W + c] = (int16_t)run;
+            if (m[b]) run = b * kBand + 63 - __builtin_clzll(m[b]);
+        }
+        v.flag[c] = run >= 0;
+        int run_dn = kNoBelow;
+#pragma unroll
+        for (int b = kCarrySmallBands - 1; b >= 0; --b) {
+            if (b < nb) v.down[(int64_t)b * W + c] = (int16_t)run_dn;
+            if (m[b]) run_dn = b * kBand + __builtin_ctzll(m[b]);
+        }
+        return;
+    }
     const int lane = threadIdx.x % kCarryCols;
     const int s = threadIdx.x / kCarryCols;
     const int c = bx * kCarryCols + lane;

@@ -135,7 +135,15 @@ __host__ __device__ inline Views views_of(const Img& g) {
 __host__ __device__ inline int items_bits(int H, int W) {
     return ((H + kBand - 1) / kBand) * ((W + kBitsCols - 1) / kBitsCols);
 }
-__host__ __device__ inline int items_carry(int, int W) { return (W + kCarryCols - 1) / kCarryCols; }
+// Images of at most kCarrySmallBands bands take one thread per column over all
+// of its bands (a work item is then kCarryCols * kCarrySlices columns); taller
+// ones split each column into kCarrySlices slices of bands.
+constexpr int kCarrySmallBands = 16;
+__host__ __device__ inline int items_carry(int H, int W) {
+    const int cols = (H + kBand - 1) / kBand <= kCarrySmallBands ? kCarryCols * kCarrySlices
+                                                                 : kCarryCols;
+    return (W + cols - 1) / cols;
+}
 __host__ __device__ inline int items_near(int H, int W) {
     return ((H + kBand - 1) / kBand) * ((W + kNearCols - 1) / kNearCols);
 }
