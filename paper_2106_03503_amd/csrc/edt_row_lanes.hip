@@ -27,7 +27,7 @@ namespace {
 
 constexpr int R = kLaneRing;
 constexpr int RB = R / 2;  // stack entries per block moved between the ring and memory
-static_assert((R & (R - 1)) == 0, "ring slots are taken modulo R with a mask");
+static_assert((R & (R - 1)) == 0 && R % RB == 0, "ring slots are taken modulo R with a mask; blocks do not wrap");
 static_assert(RB % 8 == 0, "blocks are whole 16-byte pieces of starts");
 constexpr int kBlk = 32;  // candidates per load of site rows (64 bytes per lane)
 
@@ -100,14 +100,16 @@ __device__ __forceinline__ int last_at_or_before(const uint32_t* c, int lo, int 
 template <bool kPk>
 __device__ __forceinline__ void spill_block(int b, uint32_t* sc, int16_t* rr, bool vec,
                                             LaneRing<kPk>& ring, int lane) {
+    const int s0 = b & (R - 1);  // a block never wraps round the ring
     uint32_t c[RB];
 #pragma unroll
-    for (int k = 0; k < RB; ++k) c[k] = ring.c[(b + k) & (R - 1)][lane];
+    for (int k = 0; k < RB; ++k) c[k] = ring.c[s0 + k][lane];
     if (vec) {
 #pragma unroll
-        for (int k = 0; k < RB / 4; ++k)
-            *reinterpret_cast<int4*>(sc + b + 4 * k) =
-                make_int4((int)c[4 * k], (int)c[4 * k + 1], (int)c[4 * k + 2], (int)c[4 * k + 3]);
+        for (int k = 0; k < RB / 4; ++k) {
+            const v4i x = {(int)c[4 * k], (int)c[4 * k + 1], (int)c[4 * k + 2], (int)c[4 * k + 3]};
+            *reinterpret_cast<v4i*>(sc + b + 4 * k) = x;
+        }
     } else {
 #pragma unroll
         for (int k = 0; k < RB; ++k) sc[b + k] = c[k];
@@ -116,8 +118,8 @@ __device__ __forceinline__ void spill_block(int b, uint32_t* sc, int16_t* rr, bo
         uint32_t sp[RB / 2];
 #pragma unroll
         for (int k = 0; k < RB / 2; ++k)
-            sp[k] = (uint32_t)(uint16_t)ring.s[(b + 2 * k) & (R - 1)][lane] |
-                    ((uint32_t)(uint16_t)ring.s[(b + 2 * k + 1) & (R - 1)][lane] << 16);
+            sp[k] = (uint32_t)(uint16_t)ring.s[s0 + 2 * k][lane] |
+                    ((uint32_t)(uint16_t)ring.s[s0 + 2 * k + 1][lane] << 16);
 #pragma unroll
         for (int k = 0; k < RB / 8; ++k)
             *reinterpret_cast<int4*>(rr + b + 8 * k) =
@@ -129,6 +131,7 @@ __device__ __forceinline__ void spill_block(int b, uint32_t* sc, int16_t* rr, bo
 template <bool kPk>
 __device__ __forceinline__ void fill_block(int b, const uint32_t* sc, const int16_t* rr, bool vec,
                                            LaneRing<kPk>& ring, int lane) {
+    const int s0 = b & (R - 1);  // a block never wraps round the ring
     uint32_t c[RB];
     if (vec) {
 #pragma unroll
@@ -144,7 +147,7 @@ __device__ __forceinline__ void fill_block(int b, const uint32_t* sc, const int1
         for (int k = 0; k < RB; ++k) c[k] = sc[b + k];
     }
 #pragma unroll
-    for (int k = 0; k < RB; ++k) ring.c[(b + k) & (R - 1)][lane] = c[k];
+    for (int k = 0; k < RB; ++k) ring.c[s0 + k][lane] = c[k];
     if constexpr (!kPk) {
         uint32_t sp[RB / 2];
 #pragma unroll
@@ -157,7 +160,7 @@ __device__ __forceinline__ void fill_block(int b, const uint32_t* sc, const int1
         }
 #pragma unroll
         for (int k = 0; k < RB; ++k)
-            ring.s[(b + k) & (R - 1)][lane] = (int16_t)(sp[k >> 1] >> (16 * (k & 1)));
+            ring.s[s0 + k][lane] = (int16_t)(sp[k >> 1] >> (16 * (k & 1)));
     }
 }
 
