@@ -247,7 +247,8 @@ edt_status edt_batch_autotune(edt_plan *plan, const uint8_t *mask_base, int32_t 
                               void *stream, edt_tune_report *report);
 
 /* Use the schedule (lane_w = widest image given the one-lane-per-row row
- * pass, 0..1024; largest_first != 0: images listed by decreasing size) for
+ * pass, 0..1024, which also takes only images of at most 4096 rows;
+ * largest_first != 0: images listed by decreasing size) for
  * later submissions, e.g. one that edt_batch_autotune picked for batches of
  * the same shapes.  Errors: EDT_ERR_INVALID_ARG, EDT_ERR_OUT_OF_MEMORY,
  * EDT_ERR_DEVICE. */
