@@ -19,7 +19,7 @@ namespace edt {
 
 size_t table_bytes(int n) {
     return align_up(sizeof(BatchImage) * (size_t)n, 256) +
-           kPhases * align_up(sizeof(int32_t) * ((size_t)n + 1), 256);
+           2 * kPhases * align_up(sizeof(int32_t) * ((size_t)n + 1), 256);
 }
 
 int32_t pack_table(const BatchImage* img, int n, int lane_w, uint8_t* dst, int* totals,
@@ -43,20 +43,36 @@ int32_t pack_table(const BatchImage* img, int n, int lane_w, uint8_t* dst, int* 
         if (!lanes && W > mw) mw = W;
     }
     for (int p = 0; p < kPhases; ++p) {
+        const int32_t* pre = reinterpret_cast<const int32_t*>(dst + img_bytes + p * pre_bytes);
         reinterpret_cast<int32_t*>(dst + img_bytes + p * pre_bytes)[n] = (int32_t)acc[p];
         totals[p] = (int)acc[p];
+        // coarse index: the image holding item k << s (the last image whose
+        // prefix is at most that item)
+        int32_t* first = reinterpret_cast<int32_t*>(dst + img_bytes + (kPhases + p) * pre_bytes);
+        const int s = index_shift(totals[p], n);
+        const int64_t entries = ((int64_t)totals[p] + (1ll << s) - 1) >> s;
+        int im = 0;
+        for (int64_t k = 0; k < entries; ++k) {
+            const int64_t item = k << s;
+            while (im + 1 < n && pre[im + 1] <= item) ++im;
+            first[k] = im;
+        }
     }
     *max_w = mw;
     return EDT_OK;
 }
 
-BatchTable table_view(const uint8_t* dev_table, int n) {
+BatchTable table_view(const uint8_t* dev_table, int n, const int* totals) {
     const size_t img_bytes = align_up(sizeof(BatchImage) * (size_t)n, 256);
     const size_t pre_bytes = align_up(sizeof(int32_t) * ((size_t)n + 1), 256);
     BatchTable t;
     t.img = reinterpret_cast<const BatchImage*>(dev_table);
-    for (int p = 0; p < kPhases; ++p)
+    for (int p = 0; p < kPhases; ++p) {
         t.prefix[p] = reinterpret_cast<const int32_t*>(dev_table + img_bytes + p * pre_bytes);
+        t.first[p] =
+            reinterpret_cast<const int32_t*>(dev_table + img_bytes + (kPhases + p) * pre_bytes);
+        t.shift[p] = index_shift(totals[p], n);
+    }
     t.nimg = n;
     t.mask_base = t.dist_base = t.feat_base = t.ws_base = 0;
     return t;
@@ -136,7 +152,7 @@ edt_status make_schedule(edt_plan* p, int lane_w, bool largest_first, Schedule* 
 
 hipError_t enqueue(edt_plan* p, const Schedule& sc, const uint8_t* mask_base, int32_t* dist_base,
                    int32_t* feat_base, void* workspace, hipStream_t s) {
-    edt::BatchTable t = edt::table_view(static_cast<const uint8_t*>(sc.table), p->nimg);
+    edt::BatchTable t = edt::table_view(static_cast<const uint8_t*>(sc.table), p->nimg, sc.totals);
     t.mask_base = reinterpret_cast<uintptr_t>(mask_base);
     t.dist_base = p->want_dist ? reinterpret_cast<uintptr_t>(dist_base) : 0;
     t.feat_base = p->any_feat ? reinterpret_cast<uintptr_t>(feat_base) : 0;

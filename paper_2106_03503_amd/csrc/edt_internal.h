@@ -191,6 +191,10 @@ constexpr int32_t kOutFeat = 2;
 struct BatchTable {
     const BatchImage* img;
     const int32_t* prefix[kPhases];
+    // coarse index of each phase: first[p][k] is the image holding work item
+    // k << shift[p] (at most nimg + 1 entries)
+    const int32_t* first[kPhases];
+    int shift[kPhases];
     int nimg;
     uintptr_t mask_base;
     uintptr_t dist_base;
@@ -274,30 +278,38 @@ __device__ inline Img batch_img(const BatchTable& t, int im) {
 
 // Image of work item `item` of phase p: the last image whose prefix is <= item
 // (item is the same in every lane of the wavefront).
+// Work items per entry of a phase's coarse image index, as a power of two:
+// the smallest 2^s with ceil(total / 2^s) <= n + 1 entries.
+__host__ __device__ inline int index_shift(int total, int n) {
+    int s = 0;
+    while (((int64_t)(n + 1) << s) < (int64_t)total) ++s;
+    return s;
+}
+
+// Image holding work item `item` of phase p: the last image whose prefix is at
+// most the item.  The coarse index gives an image at or before it (the one
+// holding the index entry's first item); a short forward walk over the prefix
+// (one entry covers about one image's items) finds it, instead of a binary
+// search of dependent loads over every image.
 __device__ inline int batch_image_of(const BatchTable& t, int p, int item) {
     const int32_t* pre = t.prefix[p];
-    int a = 0, b = t.nimg - 1;
-    while (a < b) {
-        const int mid = (a + b + 1) >> 1;
-        if (wave_uniform(pre[mid]) <= item)
-            a = mid;
-        else
-            b = mid - 1;
-    }
+    int a = wave_uniform(t.first[p][item >> t.shift[p]]);
+    while (a + 1 < t.nimg && wave_uniform(pre[a + 1]) <= item) ++a;
     return a;
 }
 
 // Batch tables (host side).  A table occupies table_bytes(n) bytes: the n
-// BatchImage rows, then per phase the n + 1 prefix entries, each part 256-byte
-// aligned.  pack_table writes it to host memory `dst`: images no wider than
+// BatchImage rows, then per phase the n + 1 prefix entries, then per phase the
+// coarse image index (at most n + 1 entries), each part 256-byte aligned.  pack_table writes it to host memory `dst`: images no wider than
 // lane_w (<= kLaneMaxW) take the one-lane-per-row pass; it returns the work
 // totals per phase and the widest image that takes the pass with several
 // lanes per row; EDT_ERR_TOO_LARGE if a total does not fit int32.  table_view
-// points a BatchTable at a copy of it in device memory.
+// points a BatchTable at a copy of it in device memory (totals: those
+// pack_table returned, which fix the index shifts).
 size_t table_bytes(int n);
 int32_t pack_table(const BatchImage* img, int n, int lane_w, uint8_t* dst, int* totals,
                    int* max_w);
-BatchTable table_view(const uint8_t* dev_table, int n);
+BatchTable table_view(const uint8_t* dev_table, int n, const int* totals);
 // The whole transform of a batch, enqueued on stream.
 hipError_t enqueue_batch(const BatchTable& t, const int* totals, int max_w, hipStream_t stream);
 // Argument checks of one image (shared by the single, batch and serving calls).

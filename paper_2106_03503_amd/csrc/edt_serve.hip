@@ -165,7 +165,7 @@ bool launch(edt_server* s, Group& g) {
     uint8_t* dev = s->tables + (size_t)g.slot * s->table_len;
     if (hipMemcpyAsync(dev, host, edt::table_bytes(n), hipMemcpyHostToDevice, st) != hipSuccess)
         return false;
-    edt::BatchTable t = edt::table_view(dev, n);
+    edt::BatchTable t = edt::table_view(dev, n, totals);
     t.ws_base = reinterpret_cast<uintptr_t>(s->arena);
     return edt::enqueue_batch(t, totals, max_w, st) == hipSuccess;
 }
