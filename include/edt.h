@@ -205,7 +205,9 @@ typedef struct edt_plan edt_plan;
  * persistent launch per phase over a table of the images (owned by the plan,
  * in device memory of the current device), and repeated submissions with the
  * same buffers replay a captured HIP graph.  want_dist = 0: no distances are
- * written (dist_base may then be NULL at submission).  *workspace_bytes (host)
+ * written (dist_base may then be NULL at submission); every image must then
+ * have want_feature != 0, else EDT_ERR_INVALID_ARG (an image writes at least
+ * one output).  *workspace_bytes (host)
  * receives the device workspace the submissions need.  The plan is not safe
  * for concurrent submissions from several threads.  Errors: EDT_ERR_TOO_LARGE
  * (a side, or the total of rows or work items, out of range),

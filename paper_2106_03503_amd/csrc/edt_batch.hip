@@ -193,6 +193,9 @@ edt_status edt_batch_plan(const edt_image_desc* images, int32_t n, int32_t want_
         if (st != EDT_OK) return st;
         if (d.W > EDT_BATCH_MAX_W) return EDT_ERR_TOO_LARGE;
         if (d.mask_offset < 0 || d.out_offset < 0) return EDT_ERR_INVALID_ARG;
+        // every image writes something: the one-lane-per-row pass keeps a
+        // row's stack in that row's output until the row is filled
+        if (!want_dist && !d.want_feature) return EDT_ERR_INVALID_ARG;
         edt::BatchImage& b = img[q];
         b.mask_off = d.mask_offset;
         b.mpitch = d.mask_pitch;

@@ -139,6 +139,11 @@ def test_batch_plan_validation_before_any_device_call(edt):
     assert plan([D(0, 16, 0, 8, 8, 16, 0, 1)]) == -1           # out pitch < W
     assert plan([D(0, 16, 0, 16, 8, 16, 5, 1)]) == -1          # polarity
     assert plan([D(-16, 16, 0, 16, 8, 16, 0, 1)]) == -1        # negative offset
+    # an image that writes neither distances nor features is refused (with
+    # want_dist = 0 every image must want its features)
+    assert plan([D(0, 16, 0, 16, 8, 16, 0, 0)], want_dist=0) == -1
+    assert plan([D(0, 16, 0, 16, 8, 16, 0, 1), D(256, 16, 256, 16, 8, 16, 1, 0)],
+                want_dist=0) == -1
     assert _lib.lib.edt_plan_destroy(None) == -1
 
 
