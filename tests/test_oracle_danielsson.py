@@ -40,6 +40,37 @@ def missed_mask():
     return m
 
 
+def topleft_tables():
+    """The two tables of tests/golden/danielsson_topleft_4x4.txt."""
+    out, cur = {}, None
+    with open(os.path.join(GOLDEN, "danielsson_topleft_4x4.txt")) as f:
+        for line in f:
+            line = line.split("#", 1)[0].strip()
+            if not line:
+                continue
+            if line.endswith(":"):
+                cur = line[:-1]
+                out[cur] = []
+                continue
+            out[cur].append([-1 if v == "inf" else (int(v.split(",")[0]) << 16) | int(v.split(",")[1])
+                             for v in line.split()])
+    return {k: np.array(v, dtype=np.int64) for k, v in out.items()}
+
+
+def test_first_scan_top_left_offer_decides_a_cell():
+    """A hand-traced 4 x 4 case where the first scan's top-left offer is the
+    only one that reaches the nearest site of the corner pixel (3, 3)."""
+    m = np.zeros((4, 4), np.uint8)
+    for r, c in ((0, 3), (1, 1), (3, 0)):
+        m[r, c] = 1
+    want = topleft_tables()
+    _, R1 = oracle.danielsson(m, passes=1)
+    assert np.array_equal(R1, want["first_scan"])
+    D, R = oracle.danielsson(m)
+    assert np.array_equal(R, want["final"])
+    assert D[3, 3] == 8 == oracle.separable(m)[0][3, 3]
+
+
 def test_first_scan_matches_figure():
     _, R = oracle.danielsson(workloads.paper_example(), passes=1)
     assert np.array_equal(R, positions("fig_danielssondt_b.txt"))

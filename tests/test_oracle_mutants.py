@@ -84,6 +84,9 @@ MUTANTS = [
     ("danielsson first scan sweeps the row back left to right",
      "        for (int32_t j = W - 2; j >= 0; --j) {\n            dan_offer(d, y, x, P(i, j), P(i - 1, j + 1), 1, 1);",
      "        for (int32_t j = 0; j <= W - 2; ++j) {\n            dan_offer(d, y, x, P(i, j), P(i - 1, j + 1), 1, 1);"),
+    ("danielsson first scan drops the top-left offer",
+     "            dan_offer(d, y, x, P(i, j), P(i, j - 1), 0, 1);\n            dan_offer(d, y, x, P(i, j), P(i - 1, j - 1), 1, 1);",
+     "            dan_offer(d, y, x, P(i, j), P(i, j - 1), 0, 1);"),
     ("danielsson second scan takes the vertical step from above",
      "for (int32_t j = 0; j < W; ++j) dan_offer(d, y, x, P(i, j), P(i + 1, j), 1, 0);",
      "for (int32_t j = 0; j < W; ++j) dan_offer(d, y, x, P(i, j), P(i > 0 ? i - 1 : i + 1, j), 1, 0);"),
@@ -132,6 +135,7 @@ def _pins():
     for seed in range(4):
         yield TR.test_regions_against_min_propagation, (seed,)
     yield TD.test_first_scan_matches_figure, ()
+    yield TD.test_first_scan_top_left_offer_decides_a_cell, ()
     yield TD.test_final_matches_figure_but_the_erratum, ()
     for seed in range(3):
         yield TD.test_never_below_exact_and_consistent, (seed,)
