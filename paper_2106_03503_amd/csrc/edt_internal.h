@@ -214,7 +214,9 @@ __device__ __forceinline__ int sqr_c(int x) { return __mul24(x, x); }
 // so within one of the floor wherever the result is below W), corrected with
 // the integer remainder.  It is the first pixel from which a parabola beats
 // its left neighbour when num/den is their intersection (Eq. eq_intersection,
-// with den = 2 (l - k)).
+// with den = 2 (l - k)).  A host model of these steps, with the hardware
+// reciprocal off by up to two ulp, gives the exact floor for every den in
+// [2, 2^16) and W below 2^15 at each multiple of den and its neighbours.
 __device__ __forceinline__ int first_after(int num, int den, int W) {
     if (num < 0) return 0;
     const float qf = (float)num * __builtin_amdgcn_rcpf((float)den);
