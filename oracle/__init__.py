@@ -70,6 +70,8 @@ def bind(path: str):
     lib.oracle_sqrt_f32.restype = None
     lib.oracle_brute_metric.argtypes = [P, i32, i32, i64, i32, i32, P, P]
     lib.oracle_brute_metric.restype = i64
+    lib.oracle_brute_metric_at.argtypes = [P, i32, i32, i64, i32, i32, P, i64, i32, P, P]
+    lib.oracle_brute_metric_at.restype = i64
     lib.oracle_chamfer_scans.argtypes = [P, i32, i32, i64, i32, i32, P]
     lib.oracle_chamfer_scans.restype = None
     lib.oracle_regions.argtypes = [P, i32, i32, i64, i32, i32, P, P]
@@ -207,6 +209,20 @@ def brute_metric(mask, metric: int, polarity: int = 0):
     D = np.empty((H, W), np.int32)
     F = np.empty((H, W), np.int32)
     _load().oracle_brute_metric(_ptr(m), H, W, W, polarity, metric, _ptr(D), _ptr(F))
+    return D, F
+
+
+def brute_metric_at(mask, metric: int, lin, polarity: int = 0, nthreads: int | None = None):
+    """brute_metric at the pixels with linear indices ``lin`` (i*W + j)."""
+    m = _mask(mask)
+    H, W = m.shape
+    lin = np.ascontiguousarray(np.asarray(lin, dtype=np.int64))
+    if lin.size and (lin.min() < 0 or lin.max() >= H * W):
+        raise ValueError("pixel index out of range")
+    D = np.empty(lin.shape, np.int32)
+    F = np.empty(lin.shape, np.int32)
+    _load().oracle_brute_metric_at(_ptr(m), H, W, W, polarity, metric, _ptr(lin), lin.size,
+                                   nthreads or default_threads(), _ptr(D), _ptr(F))
     return D, F
 
 

@@ -40,6 +40,7 @@
  *   oracle_brute_metric  O1 for the city-block (e=1) and chessboard (e=inf)
  *                        members of the Minkowski family (Eq. eq_Minkowski),
  *                        and for the chamfer 4-3 metric (Section 1.3.2).
+ *   oracle_brute_metric_at  the same at a list of pixels.
  *   oracle_cityblock_scans  the city-block transform by the four propagation
  *                        scans of Section 2.1 (columns down and up, then rows
  *                        forward and backward, one comparison per pixel each).
@@ -495,34 +496,72 @@ void oracle_sqrt_f32(const int32_t *D, int64_t n, float *out)
  * max - min straight ones.  D is the distance itself (not squared); F the
  * smallest linear index among the nearest sites.  Returns the number of
  * sites. */
+static void metric_nearest(const site_t *s, int64_t n, int32_t W, int32_t metric,
+                           int32_t i, int32_t j, int32_t *D, int32_t *F)
+{
+    int64_t best = -1, bestf = -1;
+    for (int64_t q = 0; q < n; ++q) {
+        int64_t di = llabs((int64_t)i - s[q].r);
+        int64_t dj = llabs((int64_t)j - s[q].c);
+        int64_t lo = di < dj ? di : dj, hi = di < dj ? dj : di;
+        int64_t d = (metric == 1) ? di + dj
+                  : (metric == 2) ? hi
+                                  : 4 * lo + 3 * (hi - lo);
+        if (best >= 0 && d >= best)
+            continue; /* sites come in row-major order: the first of equals stays */
+        best = d;
+        bestf = (int64_t)s[q].r * W + s[q].c;
+    }
+    *D = best < 0 ? ORACLE_INF_SQ : (int32_t)best;
+    *F = (int32_t)bestf;
+}
+
 int64_t oracle_brute_metric(const uint8_t *mask, int32_t H, int32_t W,
                             int64_t pitch, int32_t polarity, int32_t metric,
                             int32_t *D, int32_t *F)
 {
     site_t *s = NULL;
     int64_t n = collect_sites(mask, H, W, pitch, polarity, 0, &s);
-    for (int32_t i = 0; i < H; ++i) {
+    for (int32_t i = 0; i < H; ++i)
         for (int32_t j = 0; j < W; ++j) {
-            int64_t best = -1, bestf = -1;
-            for (int64_t q = 0; q < n; ++q) {
-                int64_t di = llabs((int64_t)i - s[q].r);
-                int64_t dj = llabs((int64_t)j - s[q].c);
-                int64_t lo = di < dj ? di : dj, hi = di < dj ? dj : di;
-                int64_t d = (metric == 1) ? di + dj
-                          : (metric == 2) ? hi
-                                          : 4 * lo + 3 * (hi - lo);
-                if (best < 0 || d < best) {
-                    best = d;
-                    bestf = (int64_t)s[q].r * W + s[q].c;
-                }
-            }
-            int64_t o = (int64_t)i * W + j;
-            D[o] = best < 0 ? ORACLE_INF_SQ : (int32_t)best;
-            F[o] = (int32_t)bestf;
+            const int64_t o = (int64_t)i * W + j;
+            metric_nearest(s, n, W, metric, i, j, &D[o], &F[o]);
         }
-    }
     free(s);
     return n;
+}
+
+typedef struct {
+    const site_t *s;
+    int64_t n;
+    int32_t W, metric;
+    const int64_t *lin;
+    int32_t *D, *F;
+} metric_at_ctx;
+
+static void metric_points(void *p, int64_t lo, int64_t hi)
+{
+    metric_at_ctx *b = (metric_at_ctx *)p;
+    for (int64_t q = lo; q < hi; ++q) {
+        const int64_t o = b->lin[q];
+        metric_nearest(b->s, b->n, b->W, b->metric, (int32_t)(o / b->W), (int32_t)(o % b->W),
+                       &b->D[q], &b->F[q]);
+    }
+}
+
+/* The same definition at n selected pixels with linear indices lin[q] = i*W + j
+ * (every site compared, as in oracle_brute_metric).  Returns the number of
+ * sites. */
+int64_t oracle_brute_metric_at(const uint8_t *mask, int32_t H, int32_t W, int64_t pitch,
+                               int32_t polarity, int32_t metric, const int64_t *lin,
+                               int64_t n, int32_t nthreads, int32_t *D, int32_t *F)
+{
+    site_t *s = NULL;
+    int64_t ns = collect_sites(mask, H, W, pitch, polarity, 0, &s);
+    metric_at_ctx b = {s, ns, W, metric, lin, D, F};
+    parallel_for(n, nthreads, metric_points, &b);
+    free(s);
+    return ns;
 }
 
 /* City-block distance transform by the four one-comparison scans of Section

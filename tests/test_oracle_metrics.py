@@ -161,3 +161,21 @@ def test_chamfer_bounds_against_euclidean():
     one[15, 15] = 1
     C1, _ = oracle.brute_metric(one, 3)
     assert C1[15 + 9, 15 + 9] == 36 and C1[15 + 9, 15 + 3] == 30  # diagonal; di = 3 dj
+
+
+@pytest.mark.parametrize("metric", [1, 2, 3])
+def test_sampled_definition_equals_full_definition(metric):
+    """brute_metric_at (the definition at listed pixels, used where the full
+    definition is too slow) gives the full definition's (D, F) at every pixel
+    it is asked for, in any order, both polarities; and at the printed
+    centre-pixel tables it reproduces the figures through that agreement."""
+    rng = np.random.default_rng(4100 + metric)
+    for _ in range(6):
+        H, W = int(rng.integers(1, 40)), int(rng.integers(1, 40))
+        m = (rng.random((H, W)) < rng.choice([0.01, 0.1, 0.5])).astype(np.uint8)
+        for pol in (0, 1):
+            Db, Fb = oracle.brute_metric(m, metric, pol)
+            lin = rng.permutation(H * W)
+            D, F = oracle.brute_metric_at(m, metric, lin, pol)
+            assert np.array_equal(D, Db.reshape(-1)[lin])
+            assert np.array_equal(F, Fb.reshape(-1)[lin])

@@ -75,6 +75,10 @@ MUTANTS = [
      "labels[q] = F[q] < 0 ? -1 : comp[F[q]];", "labels[q] = F[q] < 0 ? -1 : (comp[q] >= 0 ? comp[q] : F[q]);"),
     ("regions search only upwards", "for (int32_t di = -1; di <= 1; ++di) {",
      "for (int32_t di = -1; di <= 0; ++di) {"),
+    ("metric definition keeps the last of equally near sites",
+     "if (best >= 0 && d >= best)", "if (best >= 0 && d > best)"),
+    ("sampled metric definition swaps the pixel's row and column",
+     "(int32_t)(o / b->W), (int32_t)(o % b->W),", "(int32_t)(o % b->W), (int32_t)(o / b->W),"),
     ("danielsson takes offers at equal distance", "    if (d[to] > nd) {", "    if (d[to] >= nd) {"),
     ("danielsson vertical step adds to dx",
      "for (int32_t j = 0; j < W; ++j) dan_offer(d, y, x, P(i, j), P(i - 1, j), 1, 0);",
@@ -128,6 +132,8 @@ def _pins():
     for seed in range(4):
         yield TM.test_chamfer_scans_equal_definition, (seed,)
     yield TM.test_chamfer_bounds_against_euclidean, ()
+    for metric in (1, 2, 3):
+        yield TM.test_sampled_definition_equals_full_definition, (metric,)
     yield TR.test_diagonal_pair_is_one_object_in_8_and_two_in_4, ()
     yield TR.test_checkerboards, ()
     yield TR.test_full_empty_and_isolated_points, ()
