@@ -124,6 +124,26 @@ edt_status edt_feature(const uint8_t *mask, int32_t H, int32_t W,
                        int32_t *dist_sq, int32_t *feature, int64_t out_pitch,
                        void *workspace, size_t workspace_bytes, void *stream);
 
+/* edt_feature without a workspace argument, for callers that cannot allocate
+ * device memory (work under HIP graph capture, tight serving loops, harnesses
+ * that forbid allocation).  The workspace is a static device array of
+ * EDT_NOALLOC_SCRATCH_BYTES inside the library, one per device, held until the
+ * process ends; its address is looked up on the first call on each device.
+ * The call allocates nothing.  Same arguments, results and errors as
+ * edt_feature, without workspace and workspace_bytes, plus
+ * EDT_ERR_TOO_LARGE when edt_workspace_bytes(H, W, 1) exceeds
+ * EDT_NOALLOC_SCRATCH_BYTES (a 4096 x 4096 image fits; about 30 million
+ * pixels at most).  Every call on a device shares that device's array: calls
+ * that may overlap in time on one device (two streams, two threads) race
+ * and give undefined results.  As for edt_feature's workspace, the results do
+ * not depend on the array's contents on entry, so what the previous call left
+ * in it does not matter. */
+#define EDT_NOALLOC_SCRATCH_BYTES (64u << 20)
+edt_status edt_feature_noalloc(const uint8_t *mask, int32_t H, int32_t W,
+                               int64_t mask_pitch, int32_t polarity, int32_t metric,
+                               int32_t *dist_sq, int32_t *feature, int64_t out_pitch,
+                               void *stream);
+
 /* Voronoi regions of the objects (Section 1.1: after the transform each region
  * stands for one object point or one cluster of connected points, Figures
  * fig_voronoi and fig_blobs).  The sites are grouped into connected components

@@ -27,6 +27,7 @@ from ._lib import (  # noqa: F401
     abi_version,
     danielsson,
     feature,
+    feature_noalloc,
     library_path,
     profile_begin,
     profile_end,

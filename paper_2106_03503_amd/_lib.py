@@ -49,6 +49,8 @@ def _load():
     lib.edt_sq.restype = i32
     lib.edt_feature.argtypes = [P, i32, i32, i64, i32, i32, P, P, i64, P, sz, P]
     lib.edt_feature.restype = i32
+    lib.edt_feature_noalloc.argtypes = [P, i32, i32, i64, i32, i32, P, P, i64, P]
+    lib.edt_feature_noalloc.restype = i32
     lib.edt_sqrt_f32.argtypes = [P, P, i64, P]
     lib.edt_sqrt_f32.restype = i32
     lib.edt_regions.argtypes = [P, i32, i32, i64, i32, i32, P, P, i64, P]
@@ -162,6 +164,24 @@ def feature(mask: torch.Tensor, polarity: int = EDT_TO_OBJECT,
                             D.data_ptr() if D is not None else None, F.data_ptr(),
                             F.stride(0), ws.data_ptr(), ws.numel() * ws.element_size(),
                             _stream_ptr(stream)), "edt_feature")
+    return D, F
+
+
+def feature_noalloc(mask: torch.Tensor, out_dist: torch.Tensor | None, out_feat: torch.Tensor,
+                    polarity: int = EDT_TO_OBJECT, metric: int = EDT_METRIC_EUCLIDEAN_SQ,
+                    stream=None):
+    """edt.feature into caller-given outputs, with the library's static
+    per-device workspace instead of a workspace tensor (nothing is allocated;
+    calls that overlap on one device race).  out_dist may be None."""
+    mask = _check_mask(mask)
+    H, W = mask.shape
+    F = _check_out(out_feat, H, W, mask.device, "out_feat")
+    D = _check_out(out_dist, H, W, mask.device, "out_dist") if out_dist is not None else None
+    if D is not None and D.stride(0) != F.stride(0):
+        raise ValueError("out_dist and out_feat must share one row pitch")
+    _check(_lib.edt_feature_noalloc(mask.data_ptr(), H, W, mask.stride(0), polarity, metric,
+                                    D.data_ptr() if D is not None else None, F.data_ptr(),
+                                    F.stride(0), _stream_ptr(stream)), "edt_feature_noalloc")
     return D, F
 
 

@@ -5,8 +5,40 @@
 
 #include <math.h>
 
+#include <mutex>
+
 namespace edt {
 namespace {
+
+// Workspace of edt_feature_noalloc: every device that runs this code object
+// holds its own copy of the array until the process ends.  Host code never
+// passes the array's name to a kernel or a copy (on the host it is only a
+// stand-in for the device symbol): it looks up the array's device address
+// once per device and uses that.
+static __device__ __align__(256) uint8_t scratch[EDT_NOALLOC_SCRATCH_BYTES];
+
+constexpr int kScratchDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kScratchDevices];  // device address of scratch, per device
+
+// Device address of scratch on the current device, looked up on the first
+// call there.
+hipError_t scratch_address(void** out) {
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kScratchDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        if (!p || (reinterpret_cast<uintptr_t>(p) & 255) != 0) return hipErrorInvalidSymbol;
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return hipSuccess;
+}
 
 __global__ __launch_bounds__(256) void k_sqrt(const int32_t* __restrict__ D,
                                               float* __restrict__ out, int64_t n) {
@@ -111,6 +143,23 @@ edt_status edt_feature(const uint8_t* mask, int32_t H, int32_t W, int64_t mask_p
     if (!feature) return EDT_ERR_INVALID_ARG;
     return edt::run(mask, H, W, mask_pitch, polarity, metric, dist_sq, feature, out_pitch,
                     workspace, workspace_bytes, stream);
+}
+
+edt_status edt_feature_noalloc(const uint8_t* mask, int32_t H, int32_t W, int64_t mask_pitch,
+                               int32_t polarity, int32_t metric, int32_t* dist_sq,
+                               int32_t* feature, int64_t out_pitch, void* stream) {
+    if (!feature) return EDT_ERR_INVALID_ARG;
+    // the size limit first, so that a refused call touches no device state
+    if (H >= 1 && W >= 1 && H <= EDT_MAX_SIDE && W <= EDT_MAX_SIDE &&
+        edt::layout_for(H, W).total > (size_t)EDT_NOALLOC_SCRATCH_BYTES)
+        return EDT_ERR_TOO_LARGE;
+    const edt_status st = edt::check_image(mask, H, W, mask_pitch, polarity, metric, out_pitch);
+    if (st != EDT_OK) return st;
+    if (metric == EDT_METRIC_CHESSBOARD) return EDT_ERR_UNSUPPORTED;
+    void* ws = nullptr;
+    if (edt::scratch_address(&ws) != hipSuccess) return EDT_ERR_DEVICE;
+    return edt::run(mask, H, W, mask_pitch, polarity, metric, dist_sq, feature, out_pitch, ws,
+                    (size_t)EDT_NOALLOC_SCRATCH_BYTES, stream);
 }
 
 edt_status edt_sqrt_f32(const int32_t* dist_sq, float* dist, int64_t n, void* stream) {

@@ -104,6 +104,14 @@ def test_argument_validation_returns_before_any_launch(edt):
     assert lib.edt_danielsson(fake, 10, 10, 9, 0, big, big + 4000, 10, None) == -1
     assert lib.edt_danielsson(fake, 10, 10, 10, 3, big, big + 4000, 10, None) == -1
     assert lib.edt_danielsson(fake, 10, 10, 10, 0, big, big + 40, 10, None) == -1  # overlap
+    # the static-workspace variant: the size limit, then edt_feature's checks
+    assert lib.edt_feature_noalloc(fake, 8192, 8192, 8192, 0, 0, fake, fake, 8192, None) == -3
+    assert lib.edt_feature_noalloc(fake, 0, 10, 10, 0, 0, fake, fake, 10, None) == -3
+    assert lib.edt_feature_noalloc(fake, 10, 10, 10, 0, 0, fake, None, 10, None) == -1
+    assert lib.edt_feature_noalloc(None, 10, 10, 10, 0, 0, fake, fake, 10, None) == -1
+    assert lib.edt_feature_noalloc(fake, 10, 10, 9, 0, 0, fake, fake, 10, None) == -1
+    assert lib.edt_feature_noalloc(fake, 10, 10, 10, 3, 0, fake, fake, 10, None) == -1
+    assert lib.edt_feature_noalloc(fake, 10, 10, 10, 0, 2, fake, fake, 10, None) == -2
     # sqrt
     assert lib.edt_sqrt_f32(fake, fake, -1, None) == -1
     assert lib.edt_sqrt_f32(None, fake, 5, None) == -1
