@@ -60,6 +60,14 @@ def test_metric_matches_definition(edt, metric, k):
             assert np.array_equal(D, Db), (name, pol)
             if metric != 2:
                 assert np.array_equal(F, Fb), (name, pol)
+        else:
+            # the definition at sampled pixels (smallest index among equals)
+            rng = np.random.default_rng(2106303 + metric)
+            lin = rng.choice(m.size, size=min(m.size, int(2e9 // sites)), replace=False)
+            Db, Fb = oracle.brute_metric_at(m, metric, lin, pol)
+            assert np.array_equal(D.reshape(-1)[lin], Db), (name, pol)
+            if metric != 2:
+                assert np.array_equal(F.reshape(-1)[lin], Fb), (name, pol)
         if metric == 1:
             assert np.array_equal(D, oracle.cityblock_scans(m, pol)), (name, pol)
         if metric == 3:

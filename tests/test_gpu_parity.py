@@ -190,3 +190,40 @@ def test_mask_base_off_word_boundary(edt, W, off, pad):
     m = workloads.bernoulli(131, W, 0.02, seed=3 * W + off)
     check_exact(edt, m, 0, pitch_pad=pad, col_off=off)
     check_exact(edt, m, 1, pitch_pad=pad, col_off=off)
+
+
+@pytest.mark.parametrize("pol", [0, 1])
+def test_tallest_image_rows_next_to_the_no_site_marker(edt, pol):
+    # H = 32767, the largest side: site rows up to 32766 travel as int16 next to
+    # the "no site below" marker (INT16_MAX), squared distances reach ~2^30,
+    # and the band carries of a single image span 512 bands
+    H, W = 32767, 64
+    m = np.zeros((H, W), np.uint8)
+    m[0, 3] = m[H - 1, 60] = 1          # opposite corners of the column range
+    m[H - 1, 0] = m[0, W - 1] = 1
+    m[H // 2, 20] = 1
+    m[:, 41] = 0                         # column 41 holds no object pixel
+    m[17000:17010, 50] = 1               # a short vertical run mid-image
+    D, F = check_exact(edt, m, pol)
+    if pol == 0:
+        assert D.max() <= (H - 1) ** 2 + (W - 1) ** 2
+        assert D[H // 4, 41] > 0
+    else:
+        # inverted: the sites are everything but these pixels and column 41
+        # is all sites
+        assert (D[:, 41] == 0).all()
+
+
+@pytest.mark.parametrize("pol", [0, 1])
+def test_tall_single_image_more_than_256_bands(edt, pol):
+    # 20000 rows = 313 bands: the single-image band carries of images with more
+    # than the 256 bands whose masks the column slices keep in registers (the
+    # form that reads them again for each sweep)
+    H, W = 20000, 300
+    rng = np.random.default_rng(2106111 + pol)
+    m = (rng.random((H, W)) < 2e-4).astype(np.uint8)
+    m[:, 7] = 0
+    m[:, 150] = 0
+    m[rng.integers(0, H, 40), 150] = 1   # a column with a few far-apart sites
+    m[12345:12400, 200:203] = 1
+    check_exact(edt, m, pol)

@@ -182,3 +182,33 @@ def test_serve_wide_rows_run_alone(edt):
             D, F = srv.wait(t, timeout=60)
             Da, Fa = _alone(edt, mt, pol)
             assert torch.equal(D, Da) and torch.equal(F, Fa)
+
+
+def test_serve_request_stream_of_the_serving_workload(edt):
+    """Requests of the serving workload itself (square masks of side 128..8192,
+    Bernoulli or ellipses at density 1e-4..0.3, half with features), the
+    largest of the first 400 included, submitted together through one server
+    and each compared with the oracle's separable transform."""
+    import torch
+    dev = torch.device("cuda:0")
+    stream = workloads.serving_requests(400, 5000.0)
+    pick = list(range(34)) + sorted(range(34, 400), key=lambda q: -stream[q]["side"])[:6]
+    reqs = [stream[q] for q in pick]
+    assert max(r["side"] for r in reqs) >= 4096
+    masks = [workloads.request_mask(r) for r in reqs]
+    prepared = _prepare([(m, r["polarity"], "both" if r["want_feature"] else "dist")
+                         for m, r in zip(masks, reqs)], dev)
+    with edt.Server(32 << 30, n_streams=4) as srv:
+        tickets = _submit_all(srv, prepared)
+        results = [srv.wait(t, timeout=120) for t in tickets]
+        st = srv.stats()
+    assert st["done"] == len(reqs) and st["failed"] == 0
+    for (D, F), m, r in zip(results, masks, reqs):
+        print(f"serving request side {r['side']} {r['kind']} density {r['density']:.2g}",
+              flush=True)
+        Do, Fo = oracle.separable(m, r["polarity"])
+        np.testing.assert_array_equal(D.cpu().numpy(), Do)
+        if r["want_feature"]:
+            np.testing.assert_array_equal(F.cpu().numpy(), Fo)
+        else:
+            assert F is None
