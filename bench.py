@@ -4,7 +4,14 @@
 Workloads (--workload):
   points16k (default)  one step = one edt_feature call on a 16384 x 16384 image
                        with 30 random object points: the single-image size at
-                       which the HBM roofline is measured;
+                       which the HBM roofline is measured.  The default line
+                       also carries, as extra keys, shorter runs of the rest of
+                       the metric: "batch2048" (batched against per-image
+                       launches), "serve" (the request server at 5000 req/s and
+                       all at once, against per-image launches of the same
+                       requests) and "dense16k" (--no-extras skips them);
+  dense16k             a 16384 x 16384 image of 3200 random disks (the 4096^2
+                       disk image's density over 16 times the area);
   points16k_sq         the same image through edt_sq (distances only);
   disks4k, disks4k_inside, bernoulli256
   disks4k_regions      the disks image through edt_feature and then edt_regions
@@ -46,7 +53,15 @@ sys.path.insert(0, ROOT)
 METRIC = "Gpixel/s exact sq-EDT+feature transform and % HBM roofline; batched vs per-image"
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published peak
 SWEEP_RATES = (100.0, 250.0, 500.0, 1000.0, 2000.0, 5000.0)
-PATH_BYTES_PER_PX = 13.0  # 1 mask + 2 + 2 intermediate + 4 D + 4 F
+
+
+def path_bytes(H: int, W: int, n: int, with_feature: bool = True) -> int:
+    """Bytes the method itself must move for one image: the mask read once, the
+    outputs written once (4 B of distance, plus 4 B of feature), and the
+    intermediate as this design holds it -- the nearest site row (int16) of
+    each of the n columns holding a site, written by the vertical pass and
+    read by the row pass."""
+    return H * W * (1 + 4 + (4 if with_feature else 0)) + 2 * 2 * H * n
 
 
 def algo_bytes(kernel: str, H: int, W: int, n: int, with_dist: bool = True) -> int:
@@ -97,6 +112,11 @@ SINGLE = {
         H=4096, W=4096, polarity=0,
         desc="4096x4096 uint8 mask, 200 random filled disks (r 5-200) + Bernoulli(1e-4) "
              "points; distances outside objects"),
+    "dense16k": dict(
+        H=16384, W=16384, polarity=0,
+        desc="16384x16384 uint8 mask, 3200 random filled disks (r 5-200) + Bernoulli(1e-4) "
+             "points (the 4096^2 disk image's density of disks over 16 times the area); "
+             "distances outside objects"),
     "disks4k_inside": dict(
         H=4096, W=4096, polarity=1,
         desc="4096x4096 uint8 mask, 200 random filled disks (r 5-200) + Bernoulli(1e-4) "
@@ -132,6 +152,8 @@ def make_mask(name):
     import workloads
     if name in ("points16k", "points16k_sq"):
         return workloads.points(16384, 16384, 30)
+    if name == "dense16k":
+        return workloads.disks(16384, 16384, n_disks=3200)
     if name.startswith("disks4k"):
         return workloads.disks(4096, 4096)
     if name == "disks1k_danielsson":
@@ -206,7 +228,7 @@ def cpu_baseline(images, units_px, metric=0):
            "the oracle's two propagation scans of Danielsson's transform" if metric == "danielsson"
            else "the oracle's separable transform (vertical pass + lower envelope + fill)")
     return {"value": round(units_px / dt / 1e9, 5), "unit": "Gpixel/s", "cores": threads,
-            "kind": "oracle",
+            "cpu_model": cpu_model(), "kind": "oracle",
             "sample": f"one full pass of {how} over {what}, {threads} thread(s), {dt:.2f} s"}
 
 
@@ -278,6 +300,26 @@ def roofline(kt, algo_per_launch, workload):
             "algorithmic_bytes_per_launch": int(algo), "avg_launch_ms": round(avg_ms, 4)}
 
 
+def path_hbm(nbytes: int, ms: float) -> dict:
+    """The whole step against the bytes the method must move (path_bytes)."""
+    gbs = nbytes / (ms * 1e-3) / 1e9
+    return {"bytes_per_step": int(nbytes), "achieved_GBs": round(gbs, 1),
+            "frac": round(gbs / HBM_PEAK_GBS, 4),
+            "basis": "mask read once, outputs written once, int16 nearest site row of each "
+                     "column holding a site written and read once"}
+
+
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def base_line(args, value, ms, config):
     return {
         "metric": METRIC, "value": round(value, 3), "unit": "Gpixel/s", "n_gpus": 1,
@@ -338,10 +380,9 @@ def run_single(args):
                      "parallelism": "single GPU"})
     out["roofline"] = roofline(kt, lambda k: algo_bytes(k, H, W, n, with_dist=not sq_only),
                                args.workload)
-    path_b = PATH_BYTES_PER_PX - (4.0 if sq_only else 0.0)
-    gbs = path_b * px / (ms * 1e-3) / 1e9
-    out["path_hbm"] = {"bytes_per_px": path_b, "achieved_GBs": round(gbs, 1),
-                       "frac": round(gbs / HBM_PEAK_GBS, 4)}
+    out["roofline"]["scope"] = "the dominant kernel of the step"
+    if not dan and not conn:
+        out["path_hbm"] = path_hbm(path_bytes(H, W, n, with_feature=not sq_only), ms)
     out["roofline"]["kernel_timing"] = (f"HIP events around every launch, in a second timed "
                                         f"region of {args.steps} steps")
     out["kernels_ms_per_step"] = {k: round(v[1] / args.steps, 4) for k, v in sorted(kt.items())}
@@ -415,6 +456,9 @@ def run_batch(args):
     out["roofline"]["kernel_timing"] = (
         f"HIP events around every launch (the plan launches its kernels one by one while they "
         f"are on), in a second timed region of {max(3, args.steps // 4)} steps")
+    out["roofline"]["scope"] = "the dominant kernel of the step"
+    out["path_hbm"] = path_hbm(sum(path_bytes(m.shape[0], m.shape[1], n)
+                                   for (m, _), n in zip(imgs, ns)), ms)
     if ms_single is not None:
         out["per_image"] = {"value": round(px / (ms_single * 1e-3) / 1e9, 3),
                             "ms_per_step": round(ms_single, 4), "call": "edt_feature per image"}
@@ -433,12 +477,12 @@ def run_serve(args):
     import numpy as np
     import torch
     import paper_2106_03503_amd as edt
+    from paper_2106_03503_amd import _lib
     import workloads
     burst = args.rate <= 0  # every request at t = 0: the server's capacity
-    reqs = workloads.serving_requests(args.requests, 1000.0 if burst else args.rate)
-    if burst:
-        for r in reqs:
-            r["t"] = 0.0
+    # arrival times drawn at 1000/s and scaled: the masks do not depend on the rate
+    reqs = workloads.serving_requests(args.requests, 1000.0)
+    scale = 0.0 if burst else 1000.0 / args.rate
     dev = torch.device("cuda:0")
     print(f"serve: drawing {len(reqs)} request masks", file=sys.stderr, flush=True)
     masks_np = [workloads.request_mask(r) for r in reqs]
@@ -451,15 +495,16 @@ def run_serve(args):
         outs.append((D, F))
     torch.cuda.synchronize()
     px = sum(m.numel() for m in masks)
-    bytes_path = sum((13 if r["want_feature"] else 9) * r["side"] ** 2 for r in reqs)
+    bytes_path = sum(path_bytes(r["side"], r["side"], site_columns(m, r["polarity"]),
+                                r["want_feature"]) for m, r in zip(masks_np, reqs))
     budget = int(args.budget_gib * (1 << 30))
     stream = torch.cuda.current_stream()
 
-    def replay(srv, scale=1.0):
+    def replay(srv, sc):
         t0 = time.perf_counter()
         tickets = []
         for r, m, (D, F) in zip(reqs, masks, outs):
-            while time.perf_counter() - t0 < r["t"] * scale:
+            while time.perf_counter() - t0 < r["t"] * sc:
                 pass
             while True:
                 try:
@@ -473,19 +518,43 @@ def run_serve(args):
             srv.wait(t)
         return time.perf_counter() - t0, srv.stats()
 
+    def replays(sc, k, label):
+        runs = []
+        for q in range(k):
+            with edt.Server(budget, n_streams=args.streams) as srv:
+                wall, st = replay(srv, sc)
+            runs.append((wall, st))
+            print(f"serve: {label} replay {q + 1}/{k} {wall * 1e3:.1f} ms", file=sys.stderr,
+                  flush=True)
+        walls = [w for w, _ in runs]
+        med = sorted(range(len(runs)), key=lambda q: walls[q])[len(runs) // 2]
+        return runs[med][0], runs[med][1], walls
+
     if args.warmup > 0:  # one warm-up replay
         with edt.Server(budget, n_streams=args.streams) as srv:
-            replay(srv)
-    runs = []
-    for k in range(args.steps):
-        with edt.Server(budget, n_streams=args.streams) as srv:
-            wall, st = replay(srv)
-        runs.append((wall, st))
-        print(f"serve: replay {k + 1}/{args.steps} {wall * 1e3:.1f} ms", file=sys.stderr, flush=True)
-    walls = [w for w, _ in runs]
-    med = sorted(range(len(runs)), key=lambda q: walls[q])[len(runs) // 2]
-    wall, st = runs[med]
+            replay(srv, scale)
+    wall, st, walls = replays(scale, args.steps, "burst" if burst else f"{args.rate:g}/s")
     value = st["gpix_per_s"]
+
+    # the same requests one after the other through edt_feature / edt_sq on one
+    # stream (plain per-image launches)
+    wsz = max(edt.workspace_bytes(r["side"], r["side"]) for r in reqs)
+    ws1 = torch.empty(wsz, dtype=torch.uint8, device=dev)
+    lib = _lib.lib
+
+    def per_image():
+        for r, m, (D, F) in zip(reqs, masks, outs):
+            s_ = r["side"]
+            if F is not None:
+                st_ = lib.edt_feature(m.data_ptr(), s_, s_, s_, r["polarity"], 0, D.data_ptr(),
+                                      F.data_ptr(), s_, ws1.data_ptr(), wsz, stream.cuda_stream)
+            else:
+                st_ = lib.edt_sq(m.data_ptr(), s_, s_, s_, r["polarity"], 0, D.data_ptr(), s_,
+                                 ws1.data_ptr(), wsz, stream.cuda_stream)
+            if st_ != 0:
+                raise RuntimeError("per-image call failed")
+    ms_single, _ = timed(per_image, 2, 1, profile=False)
+
     out = base_line(args, value, wall * 1e3,
                     {"workload": SERVE_DESC.format(n=len(reqs), rate=args.rate) if not burst else
                      SERVE_DESC.replace("arriving as a Poisson stream at {rate:g}/s",
@@ -494,25 +563,26 @@ def run_serve(args):
                      "hbm_budget_GiB": args.budget_gib, "streams": args.streams,
                      "call": "edt_serve_submit / edt_serve_wait", "parallelism": "single GPU"})
     out["scaling"] = "strong"
-    offered = px / reqs[-1]["t"] / 1e9 if not burst else None
-    gbs = bytes_path / (px / (value * 1e9)) / 1e9 if value > 0 else 0.0
-    out["serve"] = {"offered_gpix_per_s": round(offered, 3) if offered else "burst",
-                    "p50_ms": round(st["p50_ns"] / 1e6, 3), "p99_ms": round(st["p99_ns"] / 1e6, 3),
-                    "mean_ms": round(st["mean_ns"] / 1e6, 3), "max_ms": round(st["max_ns"] / 1e6, 3),
-                    "launches": st["launches"], "done": st["done"], "failed": st["failed"],
-                    "rejected_busy": st["rejected_busy"],
-                    "hbm_high_water_GiB": round(st["hbm_high_water"] / (1 << 30), 3),
-                    "replay_ms": [round(w * 1e3, 2) for w in walls]}
-    out["path_hbm"] = {"bytes_per_px": round(bytes_path / px, 3), "achieved_GBs": round(gbs, 1),
-                       "frac": round(gbs / HBM_PEAK_GBS, 4)}
+    offered = px / (reqs[-1]["t"] * scale) / 1e9 if not burst else None
+    out["serve"] = serve_summary(st, walls, offered)
+    out["per_image"] = {"value": round(px / (ms_single * 1e-3) / 1e9, 3),
+                        "ms_per_pass": round(ms_single, 3),
+                        "call": "edt_feature / edt_sq per request, one stream"}
+    out["served_over_per_image"] = round(value / out["per_image"]["value"], 2)
+    out["path_hbm"] = path_hbm(bytes_path, wall * 1e3)
+    if args.capacity and not burst:
+        cwall, cst, cwalls = replays(0.0, args.steps, "burst")
+        out["capacity"] = {"gpix_per_s": round(cst["gpix_per_s"], 3),
+                           "over_per_image": round(cst["gpix_per_s"] / out["per_image"]["value"], 2),
+                           **serve_summary(cst, cwalls, None)}
     if args.sweep and not burst:
         # the same requests at other rates: the arrival times scale with 1/rate
         sweep = []
         for rate in SWEEP_RATES:
             with edt.Server(budget, n_streams=args.streams) as srv:
-                w, st_r = replay(srv, args.rate / rate)
+                w, st_r = replay(srv, 1000.0 / rate)
             sweep.append({"rate_per_s": rate,
-                          "offered_gpix_per_s": round(px / (reqs[-1]["t"] * args.rate / rate) / 1e9, 3),
+                          "offered_gpix_per_s": round(px / (reqs[-1]["t"] * 1000.0 / rate) / 1e9, 3),
                           "gpix_per_s": round(st_r["gpix_per_s"], 3),
                           "p50_ms": round(st_r["p50_ns"] / 1e6, 3),
                           "p99_ms": round(st_r["p99_ns"] / 1e6, 3),
@@ -532,6 +602,16 @@ def run_serve(args):
                         f"one after the other: " + cb["sample"])
         out["cpu_baseline"] = cb
     return out
+
+
+def serve_summary(st, walls, offered):
+    return {"offered_gpix_per_s": round(offered, 3) if offered else "burst",
+            "p50_ms": round(st["p50_ns"] / 1e6, 3), "p99_ms": round(st["p99_ns"] / 1e6, 3),
+            "mean_ms": round(st["mean_ns"] / 1e6, 3), "max_ms": round(st["max_ns"] / 1e6, 3),
+            "launches": st["launches"], "done": st["done"], "failed": st["failed"],
+            "rejected_busy": st["rejected_busy"],
+            "hbm_high_water_GiB": round(st["hbm_high_water"] / (1 << 30), 3),
+            "replay_ms": [round(w * 1e3, 2) for w in walls]}
 
 
 def main():
@@ -556,6 +636,11 @@ def main():
     ap.add_argument("--schedule", default="",
                     help="batch2048: use this schedule 'lane_w,largest_first' instead of "
                          "autotuning (e.g. 1024,1)")
+    ap.add_argument("--capacity", action="store_true",
+                    help="serve: also replay the requests all at once (the capacity)")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="points16k: skip the batch2048, serve and dense16k legs that the "
+                         "default line carries beside the headline")
     ap.add_argument("--copy-calibration", action="store_true")
     args = ap.parse_args()
 
@@ -572,7 +657,41 @@ def main():
         out = run_serve(args)
     else:
         out = run_single(args)
+        if args.workload == "points16k" and not args.no_extras:
+            out.update(extras(args))
     print(json.dumps(out), flush=True)
+
+
+def leg_args(args, **kw):
+    a = argparse.Namespace(**vars(args))
+    a.no_cpu = True
+    for k, v in kw.items():
+        setattr(a, k, v)
+    return a
+
+
+def extras(args):
+    """The rest of the metric beside the headline: the ragged batch against
+    per-image launches, the request server against per-image launches of the
+    same requests, and a dense single image at 16384^2 (shorter runs)."""
+    keep = ("value", "unit", "ms_per_step", "config", "roofline", "path_hbm",
+            "kernels_ms_per_step", "per_image")
+    print("bench: batch2048 leg", file=sys.stderr, flush=True)
+    b = run_batch(leg_args(args, workload="batch2048", steps=10, warmup=2, schedule="",
+                           no_autotune=False, no_per_image=False))
+    batch = {k: b[k] for k in keep if k in b}
+    batch["batched_over_per_image"] = b.get("batched_over_per_image")
+    batch["autotune_chosen"] = b["autotune"]["candidates"][b["autotune"]["chosen"]]
+    print("bench: serve leg", file=sys.stderr, flush=True)
+    v = run_serve(leg_args(args, workload="serve", steps=3, warmup=1, rate=5000.0,
+                           requests=400, capacity=True, sweep=False))
+    serve = {"value": v["value"], "unit": v["unit"], "config": v["config"],
+             "at_5000_per_s": v["serve"], "capacity": v["capacity"], "per_image": v["per_image"],
+             "served_over_per_image": v["served_over_per_image"], "path_hbm": v["path_hbm"]}
+    print("bench: dense16k leg", file=sys.stderr, flush=True)
+    d = run_single(leg_args(args, workload="dense16k", steps=20, warmup=3))
+    dense = {k: d[k] for k in keep if k in d}
+    return {"batch2048": batch, "serve": serve, "dense16k": dense}
 
 
 if __name__ == "__main__":
