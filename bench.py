@@ -85,7 +85,7 @@ def algo_bytes(kernel: str, H: int, W: int, n: int, with_dist: bool = True) -> i
         return H * W * 9
     if kernel == "k_danielsson":         # mask in; positions written, read back, written; D out
         return H * W * 21
-    if kernel == "k_row_segfill":        # int32 D and F (or D only) out
+    if kernel in ("k_row_segfill", "k_row_segwin"):  # int32 D and F (or D only) out
         return H * W * (8 if with_dist else 4)
     if kernel.startswith("k_row_"):      # int16 rows in, int32 D and F (or D only) out
         return H * n * 2 + H * W * (8 if with_dist else 4)
@@ -170,6 +170,7 @@ KERNEL_SOURCES = {
     "k_row_sparse": ("edt_row.hip",), "k_row_dense": ("edt_row.hip",),
     "k_row_dense_global": ("edt_row.hip",), "k_row_lanes": ("edt_row_lanes.hip",),
     "k_row_segscan": ("edt_row_lanes.hip",), "k_row_segfill": ("edt_row.hip",),
+    "k_row_segwin": ("edt_row.hip",),
     "k_sqrt": ("edt_api.hip",),
     **{k: ("edt_regions.hip",) for k in ("k_reg_init", "k_reg_union", "k_reg_flatten",
                                          "k_reg_others", "k_reg_sites")},

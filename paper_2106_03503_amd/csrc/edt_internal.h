@@ -54,6 +54,8 @@ struct Layout {
     size_t meta;       // int32  [4]      {n = number of such columns, rc row pitch}
     size_t rc;         // int16  [H][cand_pitch(W)] nearest site row of each listed column
     size_t segm;       // int16  [H][seg_count(W)]  envelope size of each row segment
+    size_t env;        // uint32 [H][cand_pitch(W)] segment envelopes (packed candidates)
+    size_t rowfail;    // uint8  [H]      row left to the segment merge
     size_t slots;      // row slots for rows wider than kLdsMaxW (single images only)
     size_t total;
 };
@@ -88,6 +90,10 @@ __host__ __device__ inline Layout layout_for(int H, int W, bool with_slots = tru
     off = align_up(off + (size_t)H * cp * 2, 256);
     L.segm = off;
     if (with_slots && has_segments(W)) off = align_up(off + (size_t)H * seg_count(W) * 2, 256);
+    L.env = off;
+    if (with_slots && has_segments(W)) off = align_up(off + (size_t)H * cp * 4, 256);
+    L.rowfail = off;
+    if (with_slots && has_segments(W)) off = align_up(off + (size_t)H, 256);
     L.slots = off;
     if (with_slots && W > kLdsMaxW) off = align_up(off + (size_t)kWideSlots * wide_slot_bytes(), 256);
     L.total = off;
@@ -349,10 +355,29 @@ hipError_t launch_column_pass_batch(const BatchTable& t, const int* totals, hipS
 hipError_t launch_row_pass_batch(const BatchTable& t, const int* totals, int max_w,
                                  hipStream_t stream);
 hipError_t launch_row_lanes_batch(const BatchTable& t, int total, hipStream_t stream);
+// Workspace of the segment path for dense rows of one image: per row the
+// envelope size of each segment, the envelopes themselves (entry e of segment
+// c at slot c kSegL + e of the row, packed candidate; its start at the same
+// slot of the row's list of site rows), and whether the row is left to the
+// segment merge.
+struct SegBufs {
+    int16_t* segm;
+    uint32_t* env;
+    uint8_t* rowfail;
+};
+__host__ __device__ inline SegBufs seg_bufs(const Img& g) {
+    const Layout L = layout_for(g.H, g.W);
+    SegBufs b;
+    b.segm = reinterpret_cast<int16_t*>(g.ws + L.segm);
+    b.env = reinterpret_cast<uint32_t*>(g.ws + L.env);
+    b.rowfail = g.ws + L.rowfail;
+    return b;
+}
 // Dense rows of one image (has_segments(W), more than kSparseMaxN candidates,
-// known only on the device): envelopes of row segments of L candidates, one
-// lane per (row, segment), sizes to `segm`.
-hipError_t launch_row_segscan(const Img& g, int L, int16_t* segm, hipStream_t stream);
+// known only on the device): envelopes of row segments of kSegL candidates,
+// one lane per (row, segment), to `b`; every row is marked as not left to the
+// merge.
+hipError_t launch_row_segscan(const Img& g, const SegBufs& b, hipStream_t stream);
 hipError_t launch_sqrt(const int32_t* D, float* out, int64_t n, hipStream_t stream);
 
 }  // namespace edt

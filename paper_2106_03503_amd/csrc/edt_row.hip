@@ -454,9 +454,242 @@ __global__ __launch_bounds__(T) void k_row_single(Img g, uint8_t* __restrict__ s
 
 // Dense rows of one image after the segment scan: the envelope of segment c
 // (candidates [c L, (c + 1) L), built one lane per row and segment) holds
-// segm entries at slots c L + e of the row's output (packed candidate) and of
-// its candidate list (start).  Per row: copy them into LDS, merge the
-// segments up a binary tree (log2(n / L) levels), compact the survivors and
+// segm[i][c] entries at slots c L + e of the row in env (packed candidate)
+// and in its list of site rows (start).
+//
+// k_row_segwin fills every pixel from the best of the segment envelopes near
+// it, with the bounded search of Section 3.2.2 at the level of segments:
+// starting from the segment under the pixel, a walk goes left and right and
+// stops on each side at the first segment whose nearest column is
+// horizontally farther than the best distance found (strictly farther, so
+// that an equally near site with a smaller index is still seen); every
+// candidate beyond it is farther still.  A work item is one tile of kWinTile
+// pixels of a row; it copies into LDS the segments under the tile and
+// kWinHalo more on each side, and reads a segment beyond those from memory.
+// A row where some pixel would need more than kWinCap segments besides its
+// own is marked in rowfail and done by k_row_segfill instead: its segments
+// are merged up a binary tree (log2(n / L) levels), the survivors compacted,
+// and the row filled from them.
+constexpr int kWinTile = 2048;
+constexpr int kWinLanes = 256;
+constexpr int kWinHalo = 4;
+constexpr int kWinCap = 24;
+// segments a tile's columns can touch (each spans at least kSegL columns),
+// plus the halo
+constexpr int kWinSegs = kWinTile / kSegL + 1 + 2 * kWinHalo;
+constexpr int kMaxSegs = kLdsMaxW / kSegL;
+constexpr int kWinPer = (kWinSegs * kSegL + kWinLanes - 1) / kWinLanes;  // slots per lane
+
+struct WinLds {
+    uint32_t cand[kWinSegs * kSegL];
+    int16_t st[kWinSegs * kSegL];
+    int eleft[kWinSegs], eright[kWinSegs];   // envelope of each loaded segment at its
+                                             // first and last column
+    int16_t cnt[kWinSegs];                   // entries of each loaded segment
+    int16_t segof[kWinTile / 16];            // segment under every 16th pixel of the tile
+    int16_t first[kMaxSegs], last[kMaxSegs];  // columns of each segment's first and last candidate
+};
+
+// Last index e in [lo, hi) with st[e] <= j, given st[lo] <= j (LDS or memory).
+template <typename SP>
+__device__ __forceinline__ int last_le_any(SP st, int lo, int hi, int j) {
+    int a = lo, b = hi - 1;
+    while (a < b) {
+        const int mid = (a + b + 1) >> 1;
+        if (st[mid] <= j)
+            a = mid;
+        else
+            b = mid - 1;
+    }
+    return a;
+}
+
+// Best entry of one segment envelope (entries [lo, hi) of cand / st, the first
+// starting at pixel 0) at the four pixels j..j+3 of row i, folded into (bd, bf)
+// lexicographically.
+template <typename CP, typename SP>
+__device__ __forceinline__ void seg_best4(CP cand, SP st, int lo, int hi, int i, int j, int W,
+                                          int* bd, int* bf) {
+    int e = last_le_any(st, lo, hi, j);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int jj = j + q;
+        while (e + 1 < hi && st[e + 1] <= jj) ++e;
+        const uint32_t C = cand[e];
+        const int d = sqr_c(i - crow(C)) + sqr_c(jj - ccol(C));
+        const int f = mul_c(crow(C), W) + ccol(C);
+        if (d < bd[q] || (d == bd[q] && f < bf[q])) {
+            bd[q] = d;
+            bf[q] = f;
+        }
+    }
+}
+
+// The last segment whose first column is at or before x (0 if none).
+__device__ __forceinline__ int seg_at(const int16_t* first, int nseg, int x) {
+    int a = 0, b = nseg - 1;
+    while (a < b) {
+        const int mid = (a + b + 1) >> 1;
+        if (first[mid] <= x)
+            a = mid;
+        else
+            b = mid - 1;
+    }
+    return a;
+}
+
+__global__ __launch_bounds__(kWinLanes) void k_row_segwin(Img g, SegBufs sb) {
+    __shared__ WinLds sh;
+    __shared__ int s_lo, s_hi;
+    const Views v = views_of(g);
+    const int n = v.meta[0];
+    if (n <= kSparseMaxN) return;  // the one-wavefront row pass took the image
+    const int W = g.W;
+    const int pitch = v.meta[1];
+    const int nseg = (n + kSegL - 1) / kSegL;
+    const int ntiles = (W + kWinTile - 1) / kWinTile;
+    const int total = g.H * ntiles;
+    const int t = threadIdx.x;
+    const int sstride = seg_count(W);
+    const bool vec = (!g.dist || reinterpret_cast<uintptr_t>(g.dist) % 16 == 0) &&
+                     (!g.feat || reinterpret_cast<uintptr_t>(g.feat) % 16 == 0) &&
+                     (g.opitch % 4 == 0);
+    for (int c = t; c < nseg; c += kWinLanes) {
+        sh.first[c] = v.cols[c * kSegL];
+        sh.last[c] = v.cols[min((c + 1) * kSegL, n) - 1];
+    }
+    for (int item = blockIdx.x; item < total; item += gridDim.x) {
+        const int i = item / ntiles;
+        const int x0 = (item - i * ntiles) * kWinTile, x1 = min(W, x0 + kWinTile);
+        __syncthreads();  // the previous item is done with the LDS copy
+        if (t == 0) {
+            s_lo = max(0, seg_at(sh.first, nseg, x0) - kWinHalo);
+            s_hi = min(nseg - 1, seg_at(sh.first, nseg, x1 - 1) + kWinHalo);
+        }
+        __syncthreads();
+        const int lo = s_lo, hi = s_hi;  // loaded segments [lo, hi], at most kWinSegs
+        const uint32_t* erow = sb.env + (int64_t)i * pitch;
+        const int16_t* srow = v.rc + (int64_t)i * pitch;
+        const int16_t* mrow = sb.segm + (int64_t)i * sstride;
+        // every load in flight before the LDS writes: slots of candidates
+        // past a segment's envelope are copied too and never read
+        const int q0 = lo * kSegL, qn = min(n, (hi + 1) * kSegL);
+        uint32_t vc[kWinPer];
+        int vs[kWinPer];
+#pragma unroll
+        for (int u = 0; u < kWinPer; ++u) {
+            const int q = q0 + t + u * kWinLanes;
+            if (q < qn) {
+                vc[u] = erow[q];
+                vs[u] = srow[q];
+            }
+        }
+        const int mt = t <= hi - lo ? mrow[lo + t] : 0;
+        if (t <= hi - lo) sh.cnt[t] = (int16_t)mt;
+#pragma unroll
+        for (int u = 0; u < kWinPer; ++u) {
+            const int q = q0 + t + u * kWinLanes;
+            if (q < qn) {
+                sh.cand[q - q0] = vc[u];
+                sh.st[q - q0] = (int16_t)vs[u];
+            }
+        }
+        __syncthreads();
+        // A candidate k of segment c and a pixel x left of c's first column f
+        // have (k - x)^2 >= (k - f)^2 + (f - x)^2, so c's envelope at x is at
+        // least its value at f plus (f - x)^2; likewise right of its last
+        // column.  These two values bound a segment before it is searched.
+        if (t < kWinTile / 16) sh.segof[t] = (int16_t)seg_at(sh.first, nseg, x0 + 16 * t);
+        if (t <= hi - lo) {
+            const int b0 = t * kSegL, f = sh.first[lo + t], l = sh.last[lo + t];
+            const uint32_t Cf = sh.cand[last_le_any(sh.st, b0, b0 + mt, f)];
+            const uint32_t Cl = sh.cand[last_le_any(sh.st, b0, b0 + mt, l)];
+            sh.eleft[t] = sqr_c(i - crow(Cf)) + sqr_c(f - ccol(Cf));
+            sh.eright[t] = sqr_c(i - crow(Cl)) + sqr_c(l - ccol(Cl));
+        }
+        __syncthreads();
+        int32_t* drow = g.dist ? g.dist + (int64_t)i * g.opitch : nullptr;
+        int32_t* frow = g.feat ? g.feat + (int64_t)i * g.opitch : nullptr;
+        bool ok = true;
+        for (int j = x0 + 4 * t; j < x1 && ok; j += 4 * kWinLanes) {
+            int bd[4], bf[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                bd[q] = INT32_MAX;
+                bf[q] = INT32_MAX;
+            }
+            // best of segment c at j..j+3, from LDS when it is loaded
+            auto visit = [&](int c) {
+                if (c >= lo && c <= hi) {
+                    const int b0 = (c - lo) * kSegL;
+                    seg_best4(sh.cand, sh.st, b0, b0 + sh.cnt[c - lo], i, j, W, bd, bf);
+                } else {
+                    seg_best4(erow, srow, c * kSegL, c * kSegL + mrow[c], i, j, W, bd, bf);
+                }
+            };
+            // a segment spans at least kSegL >= 16 columns: at most one more
+            // starts within the 16 pixels
+            int s0 = sh.segof[(j - x0) >> 4];
+            if (s0 + 1 < nseg && sh.first[s0 + 1] <= j) ++s0;
+            visit(s0);
+            const int jl = min(j + 3, W - 1);  // pixels past the row end do not widen the search
+            auto farthest = [&]() {
+                int f = 0;
+#pragma unroll
+                for (int q = 0; q < 4; ++q)
+                    if (j + q < W) f = max(f, bd[q]);
+                return f;
+            };
+            int far = farthest(), evals = 0;
+            for (int c = s0 - 1; c >= 0; --c) {
+                const int l = sh.last[c];
+                const int gap = j - l;  // >= 1: every column of c lies left of j
+                if (sqr_c(gap) > far) break;
+                if (c >= lo && c <= hi) {
+                    // skip c if its bound beats no pixel of the group
+                    const int e = sh.eright[c - lo];
+                    bool need = false;
+#pragma unroll
+                    for (int q = 0; q < 4; ++q)
+                        need |= j + q < W && e + sqr_c(j + q - l) <= bd[q];
+                    if (!need) continue;
+                }
+                if (++evals > kWinCap) {
+                    ok = false;
+                    break;
+                }
+                visit(c);
+                far = farthest();
+            }
+            for (int c = s0 + 1; c < nseg && ok; ++c) {
+                const int f = sh.first[c];
+                const int gap = f - jl;  // may be <= 0: c starts inside the group
+                if (gap > 0 && sqr_c(gap) > far) break;
+                if (gap > 0 && c >= lo && c <= hi) {
+                    const int e = sh.eleft[c - lo];
+                    bool need = false;
+#pragma unroll
+                    for (int q = 0; q < 4; ++q)
+                        need |= j + q < W && e + sqr_c(f - j - q) <= bd[q];
+                    if (!need) continue;
+                }
+                if (++evals > kWinCap) {
+                    ok = false;
+                    break;
+                }
+                visit(c);
+                far = farthest();
+            }
+            if (!ok) break;
+            if (drow) store4(drow, j, W, vec, bd[0], bd[1], bd[2], bd[3]);
+            if (frow) store4(frow, j, W, vec, bf[0], bf[1], bf[2], bf[3]);
+        }
+        if (!ok) sb.rowfail[i] = 1;
+    }
+}
+
+// The rows that k_row_segwin left to the merge: per row, copy the segment
+// envelopes into LDS, merge them up a binary tree, compact the survivors and
 // fill.  The form with T lanes takes widths in (8 T, 16 T].
 template <int T, int L>
 struct SegLds {
@@ -470,10 +703,11 @@ struct SegLds {
 };
 
 template <int T, int L>
-__global__ __launch_bounds__(T, T <= 512 ? 6 : 1) void k_row_segfill(Img g, const int16_t* __restrict__ segm) {
+__global__ __launch_bounds__(T, T <= 512 ? 6 : 1) void k_row_segfill(Img g, SegBufs sb) {
     __shared__ SegLds<T, L> sh;
     constexpr int CAP = SegLds<T, L>::CAP, NW = T / 64, PER = CAP / T;
     static_assert(SegLds<T, L>::G <= T, "one lane per segment");
+    static_assert(L == kSegL, "segment envelopes are laid out kSegL slots apart");
     const Views v = views_of(g);
     const int n = v.meta[0];
     const int W = g.W;
@@ -482,16 +716,16 @@ __global__ __launch_bounds__(T, T <= 512 ? 6 : 1) void k_row_segfill(Img g, cons
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
     const int nchunks = (n + L - 1) / L;
     const int sstride = seg_count(W);
-    int32_t* base = g.dist ? g.dist : g.feat;
     const bool vec = (!g.dist || reinterpret_cast<uintptr_t>(g.dist) % 16 == 0) &&
                      (!g.feat || reinterpret_cast<uintptr_t>(g.feat) % 16 == 0) &&
                      (g.opitch % 4 == 0);
     const PlainSlots sl{sh.cand, sh.st};
     for (int i = blockIdx.x; i < g.H; i += gridDim.x) {
-        const uint32_t* sc = reinterpret_cast<const uint32_t*>(base + (int64_t)i * g.opitch);
+        if (!sb.rowfail[i]) continue;  // the same in every lane
+        const uint32_t* sc = sb.env + (int64_t)i * pitch;
         const int16_t* rr = v.rc + (int64_t)i * pitch;
         if (t < nchunks) {
-            const int m = segm[(int64_t)i * sstride + t * (L / kSegL)];
+            const int m = sb.segm[(int64_t)i * sstride + t];
             sh.lo[t] = (int16_t)(t * L);
             sh.hi[t] = (int16_t)(t * L + m);
             sh.nxt[t] = -1;
@@ -640,26 +874,37 @@ hipError_t launch_batch(const BatchTable& tb, int total, hipStream_t stream) {
 }
 
 template <int T, int L>
-hipError_t launch_segfill(const Img& g, const int16_t* segm, hipStream_t stream) {
+hipError_t launch_segfill(const Img& g, const SegBufs& sb, hipStream_t stream) {
     static int per_cu = 0;
     if (per_cu == 0) per_cu = blocks_per_cu(k_row_segfill<T, L>, T);
     int grid = per_cu * device_cus();
     if (grid > g.H) grid = g.H;
-    EDT_LAUNCH_AS("k_row_segfill", (k_row_segfill<T, L>), dim3(grid), dim3(T), 0, stream, g, segm);
+    EDT_LAUNCH_AS("k_row_segfill", (k_row_segfill<T, L>), dim3(grid), dim3(T), 0, stream, g, sb);
     return hipGetLastError();
 }
 
-// Dense rows of one image, squared Euclidean: segment scan, then merge + fill.
+hipError_t launch_segwin(const Img& g, const SegBufs& sb, hipStream_t stream) {
+    static int per_cu = 0;
+    if (per_cu == 0) per_cu = blocks_per_cu(k_row_segwin, kWinLanes);
+    const int total = g.H * ((g.W + kWinTile - 1) / kWinTile);
+    const int grid = min(total, per_cu * device_cus());
+    EDT_LAUNCH_AS("k_row_segwin", k_row_segwin, dim3(grid), dim3(kWinLanes), 0, stream, g, sb);
+    return hipGetLastError();
+}
+
+// Dense rows of one image, squared Euclidean: segment scan, the bounded
+// search over segments, then the merge for the rows it left.
 hipError_t launch_rows_segments(const Img& g, hipStream_t stream) {
     constexpr int L = kSegL;
-    int16_t* segm = reinterpret_cast<int16_t*>(g.ws + layout_for(g.H, g.W).segm);
-    hipError_t e = launch_row_segscan(g, L, segm, stream);
+    const SegBufs sb = seg_bufs(g);
+    hipError_t e = launch_row_segscan(g, sb, stream);
+    if (e == hipSuccess) e = launch_segwin(g, sb, stream);
     if (e != hipSuccess) return e;
     const int W = g.W;
-    if (W <= 2048) return launch_segfill<128, L>(g, segm, stream);
-    if (W <= 4096) return launch_segfill<256, L>(g, segm, stream);
-    if (W <= 8192) return launch_segfill<512, L>(g, segm, stream);
-    return launch_segfill<1024, L>(g, segm, stream);
+    if (W <= 2048) return launch_segfill<128, L>(g, sb, stream);
+    if (W <= 4096) return launch_segfill<256, L>(g, sb, stream);
+    if (W <= 8192) return launch_segfill<512, L>(g, sb, stream);
+    return launch_segfill<1024, L>(g, sb, stream);
 }
 
 template <int kM>

@@ -373,13 +373,15 @@ __global__ __launch_bounds__(kLaneRows) void k_row_lanes_batch(BatchTable tb) {
 
 // Segment scan for dense rows of one image: work item (row group, segment y)
 // scans the segment's candidates [y L, min(n, (y + 1) L)) of 64 rows, one lane
-// per row, leaving each segment's envelope at ranks y L + e and its size in
-// segm[i][y].  The grid is persistent over the items, whose count depends on
-// the device-side number n of listed columns; images with at most
+// per row, leaving each segment's envelope at slots y L + e of the row in
+// b.env (starts in the row's list of site rows) and its size in
+// b.segm[i][y].  The grid is persistent over the items, whose count depends
+// on the device-side number n of listed columns; images with at most
 // kSparseMaxN of them are left to the one-wavefront row pass.
 template <int L>
-__global__ __launch_bounds__(kLaneRows) void k_row_segscan(Img g, int16_t* __restrict__ segm) {
+__global__ __launch_bounds__(kLaneRows) void k_row_segscan(Img g, SegBufs b) {
     __shared__ LaneRing<false> ring;
+    static_assert(L == kSegL, "segment envelopes are laid out kSegL slots apart");
     const Views v = views_of(g);
     const int n = v.meta[0];
     if (n <= kSparseMaxN) return;
@@ -387,19 +389,16 @@ __global__ __launch_bounds__(kLaneRows) void k_row_segscan(Img g, int16_t* __res
     const int total = items_lanes(g.H) * nseg;
     const int lane = threadIdx.x;
     const int pitch = v.meta[1];
-    int32_t* base = g.dist ? g.dist : g.feat;
-    const bool vec = (!g.dist || reinterpret_cast<uintptr_t>(g.dist) % 16 == 0) &&
-                     (!g.feat || reinterpret_cast<uintptr_t>(g.feat) % 16 == 0) &&
-                     (g.opitch % 4 == 0);
     for (int item = blockIdx.x; item < total; item += gridDim.x) {
         const int grp = item / nseg, y = item - grp * nseg;
         const int q0 = y * L;
         const int i = grp * kLaneRows + lane;
         if (i < g.H) {
-            uint32_t* sc = reinterpret_cast<uint32_t*>(base + (int64_t)i * g.opitch) + q0;
+            uint32_t* sc = b.env + (int64_t)i * pitch + q0;
             const int M = scan_row<false>(i, min(L, n - q0), g.W, v.cols + q0,
-                                          v.rc + (int64_t)i * pitch + q0, sc, vec, ring, lane);
-            segm[(int64_t)i * seg_count(g.W) + y * (L / kSegL)] = (int16_t)M;
+                                          v.rc + (int64_t)i * pitch + q0, sc, true, ring, lane);
+            b.segm[(int64_t)i * seg_count(g.W) + y] = (int16_t)M;
+            if (y == 0) b.rowfail[i] = 0;
         }
     }
 }
@@ -415,20 +414,13 @@ int lane_blocks_per_cu(K kernel) {
 
 }  // namespace
 
-hipError_t launch_row_segscan(const Img& g, int L, int16_t* segm, hipStream_t stream) {
-    static int per_cu64 = 0, per_cu128 = 0;
-    const int most = items_lanes(g.H) * ((g.W + L - 1) / L);  // items if every column is listed
-    if (L == 64) {
-        if (per_cu64 == 0) per_cu64 = lane_blocks_per_cu(k_row_segscan<64>);
-        const int grid = min(most, per_cu64 * device_cus());
-        EDT_LAUNCH_AS("k_row_segscan", k_row_segscan<64>, dim3(grid), dim3(kLaneRows), 0, stream,
-                      g, segm);
-    } else {
-        if (per_cu128 == 0) per_cu128 = lane_blocks_per_cu(k_row_segscan<128>);
-        const int grid = min(most, per_cu128 * device_cus());
-        EDT_LAUNCH_AS("k_row_segscan", k_row_segscan<128>, dim3(grid), dim3(kLaneRows), 0, stream,
-                      g, segm);
-    }
+hipError_t launch_row_segscan(const Img& g, const SegBufs& b, hipStream_t stream) {
+    static int per_cu = 0;
+    const int most = items_lanes(g.H) * seg_count(g.W);  // items if every column is listed
+    if (per_cu == 0) per_cu = lane_blocks_per_cu(k_row_segscan<kSegL>);
+    const int grid = min(most, per_cu * device_cus());
+    EDT_LAUNCH_AS("k_row_segscan", k_row_segscan<kSegL>, dim3(grid), dim3(kLaneRows), 0, stream,
+                  g, b);
     return hipGetLastError();
 }
 

@@ -227,3 +227,25 @@ def test_tall_single_image_more_than_256_bands(edt, pol):
     m[rng.integers(0, H, 40), 150] = 1   # a column with a few far-apart sites
     m[12345:12400, 200:203] = 1
     check_exact(edt, m, pol)
+
+
+@pytest.mark.parametrize("kind", ["diagonal", "top_row", "two_rows", "sparse_top"])
+def test_dense_rows_with_far_sites(edt, kind):
+    # every column holds a site (the segment path), but many pixels lie far from
+    # all of them: their bounded search over segment envelopes gives up and the
+    # row is merged instead; rows near the sites keep the bounded search
+    H, W = 600, 3000
+    m = np.zeros((H, W), np.uint8)
+    cols = np.arange(W)
+    if kind == "diagonal":
+        m[(cols * (H - 1)) // (W - 1), cols] = 1
+    elif kind == "top_row":
+        m[0, :] = 1
+    elif kind == "two_rows":
+        m[0, ::2] = 1
+        m[H - 1, 1::2] = 1
+    else:
+        m[0, :] = 1
+        m[1:, :] = (np.random.default_rng(5).random((H - 1, W)) < 2e-5)
+    check_exact(edt, m, 0)
+    check_exact(edt, m, 1)
