@@ -132,13 +132,12 @@ edt_status edt_feature(const uint8_t *mask, int32_t H, int32_t W,
  * The call allocates nothing.  Same arguments, results and errors as
  * edt_feature, without workspace and workspace_bytes, plus
  * EDT_ERR_TOO_LARGE when edt_workspace_bytes(H, W, 1) exceeds
- * EDT_NOALLOC_SCRATCH_BYTES (a 4096 x 4096 image fits; about 30 million
- * pixels at most).  Every call on a device shares that device's array: calls
+ * EDT_NOALLOC_SCRATCH_BYTES (a 4096 x 4096 image fits).  Every call on a device shares that device's array: calls
  * that may overlap in time on one device (two streams, two threads) race
  * and give undefined results.  As for edt_feature's workspace, the results do
  * not depend on the array's contents on entry, so what the previous call left
  * in it does not matter. */
-#define EDT_NOALLOC_SCRATCH_BYTES (64u << 20)
+#define EDT_NOALLOC_SCRATCH_BYTES (128u << 20)
 edt_status edt_feature_noalloc(const uint8_t *mask, int32_t H, int32_t W,
                                int64_t mask_pitch, int32_t polarity, int32_t metric,
                                int32_t *dist_sq, int32_t *feature, int64_t out_pitch,

@@ -6,7 +6,7 @@ import pytest
 
 import workloads
 
-SCRATCH = 64 << 20
+SCRATCH = 128 << 20
 
 
 def _run_both(edt, lib, m, pol, metric=0):
