@@ -55,7 +55,7 @@ extern "C" {
 typedef int32_t edt_status;
 #define EDT_OK 0
 #define EDT_ERR_INVALID_ARG (-1)   /* null pointer, bad pitch, bad enum, short workspace */
-#define EDT_ERR_UNSUPPORTED (-2)   /* a metric (or metric + output) not provided */
+#define EDT_ERR_UNSUPPORTED (-2)   /* reserved: a metric or output not provided */
 #define EDT_ERR_TOO_LARGE (-3)     /* H or W outside [1, EDT_MAX_SIDE] */
 #define EDT_ERR_OUT_OF_MEMORY (-4) /* a host or library-owned allocation failed */
 #define EDT_ERR_BUSY (-5)          /* a server's memory budget or queue is full */
@@ -114,9 +114,10 @@ edt_status edt_sq(const uint8_t *mask, int32_t H, int32_t W, int64_t mask_pitch,
 
 /* Exact distance plus feature transform (the nearest site's index, Section
  * 3.3: the column that gives the minimum, extended with the site's row from
- * the vertical pass), for the squared Euclidean, city-block and chamfer 4-3
- * metrics (chessboard: EDT_ERR_UNSUPPORTED, because its ties between sites of
- * one column are not decided by the vertical pass).  Same arguments as edt_sq, plus
+ * the vertical pass), for every metric.  Under the chessboard metric the
+ * sites at the smallest distance D from a pixel are those of the square of
+ * half-side D around it, and the feature is its topmost site, leftmost among
+ * those (the smallest index).  Same arguments as edt_sq, plus
  *   dist_sq     may be NULL when only the features are wanted
  *   feature     device, int32, H x W with row pitch out_pitch elements; written */
 edt_status edt_feature(const uint8_t *mask, int32_t H, int32_t W,

@@ -75,9 +75,6 @@ static edt_status run(const uint8_t* mask, int32_t H, int32_t W, int64_t mask_pi
     edt_status st = check_image(mask, H, W, mask_pitch, polarity, metric, out_pitch);
     if (st != EDT_OK) return st;
     if (!dist && !feat) return EDT_ERR_INVALID_ARG;
-    // chessboard ties can sit at other rows of a column than its nearest site,
-    // which the vertical pass does not keep: no exact feature transform
-    if (feat && metric == EDT_METRIC_CHESSBOARD) return EDT_ERR_UNSUPPORTED;
     const Layout L = layout_for(H, W);
     if (!workspace || workspace_bytes < L.total) return EDT_ERR_INVALID_ARG;
     if ((reinterpret_cast<uintptr_t>(workspace) & 255) != 0) return EDT_ERR_INVALID_ARG;
@@ -155,7 +152,6 @@ edt_status edt_feature_noalloc(const uint8_t* mask, int32_t H, int32_t W, int64_
         return EDT_ERR_TOO_LARGE;
     const edt_status st = edt::check_image(mask, H, W, mask_pitch, polarity, metric, out_pitch);
     if (st != EDT_OK) return st;
-    if (metric == EDT_METRIC_CHESSBOARD) return EDT_ERR_UNSUPPORTED;
     void* ws = nullptr;
     if (edt::scratch_address(&ws) != hipSuccess) return EDT_ERR_DEVICE;
     return edt::run(mask, H, W, mask_pitch, polarity, metric, dist_sq, feature, out_pitch, ws,

@@ -58,11 +58,49 @@ __device__ __forceinline__ int dist_to(uint32_t C, int i, int j) {
     return 3 * max(ar, ac) + min(ar, ac);
 }
 
+// Ties under the chessboard metric.  At chessboard distance D from pixel
+// (i, j) every site of the square [i - D, i + D] x [j - D, j + D] lies at
+// exactly D (D being the smallest distance), so the nearest site with the
+// smallest index is the square's topmost one, leftmost among those.  A column
+// k with max(|i - r_k|, |j - k|) = D offers its topmost site at or below row
+// i - D, which may lie above its nearest site r_k; two columns that tie are
+// therefore compared on that row, then on the column.  The row is read from
+// the column pass: the band's site bits from row i - D on, else the first
+// site row below the band.  Where two columns tie over several pixels D is
+// constant there (both costs are flat), so the comparison is the same at each
+// of them and a column right of another still beats it on a suffix of the
+// row.
+struct TieCtx {
+    const uint64_t* bits;  // [nb][W] site bits of each band column
+    const int16_t* down;   // [nb][W] first site row below each band
+    int W;
+};
+
+// First site row at or after row x (x < 0 counts as 0) in column c, which
+// holds a site at or after x.
+__device__ __forceinline__ int next_site(const TieCtx& tc, int c, int x) {
+    x = max(x, 0);
+    const int64_t at = (int64_t)(x >> 6) * tc.W + c;
+    const uint64_t m = tc.bits[at] >> (x & 63);
+    return m ? x + __builtin_ctzll(m) : tc.down[at];
+}
+
 // Does B (a column right of A's) beat A at pixel j of row i?
 template <int kM>
-__device__ __forceinline__ bool beats(uint32_t B, uint32_t A, int i, int j) {
+__device__ __forceinline__ bool beats(uint32_t B, uint32_t A, int i, int j, const TieCtx& tc) {
     const int fb = dist_to<kM>(B, i, j), fa = dist_to<kM>(A, i, j);
-    return fb < fa || (fb == fa && crow(B) < crow(A));
+    if (fb != fa) return fb < fa;
+    if (kM == 2) return next_site(tc, ccol(B), i - fb) < next_site(tc, ccol(A), i - fa);
+    return crow(B) < crow(A);
+}
+
+// Feature of pixel (i, j) owned by candidate C at distance d: the site's
+// linear index (under the chessboard metric, the topmost site of C's column
+// at distance d).
+template <int kM>
+__device__ __forceinline__ int feature_of(uint32_t C, int i, int d, int W, const TieCtx& tc) {
+    const int r = kM == 2 ? next_site(tc, ccol(C), i - d) : crow(C);
+    return mul_c(r, W) + ccol(C);
 }
 
 // First pixel j in [0, W] from which B beats A (W: never inside the row); B
@@ -75,7 +113,8 @@ __device__ __forceinline__ bool beats(uint32_t B, uint32_t A, int i, int j) {
 //   between from the first j with 2j > fb - fa + l + k.
 //   Chessboard and chamfer 4-3: the suffix is found by bisection.
 template <int kM>
-__device__ __forceinline__ int first_win(uint32_t A, uint32_t B, int i, int W) {
+__device__ __forceinline__ int first_win(uint32_t A, uint32_t B, int i, int W,
+                                         const TieCtx& tc) {
     const int k = ccol(A), l = ccol(B), rk = crow(A), rl = crow(B);
     const int t = rl < rk ? 1 : 0;  // B wins ties
     if (kM == 0) {
@@ -93,7 +132,7 @@ __device__ __forceinline__ int first_win(uint32_t A, uint32_t B, int i, int W) {
         int lo = 0, hi = W;
         while (lo < hi) {
             const int mid = (lo + hi) >> 1;
-            if (beats<kM>(B, A, i, mid))
+            if (beats<kM>(B, A, i, mid, tc))
                 hi = mid;
             else
                 lo = mid + 1;
@@ -132,7 +171,7 @@ __device__ void merge_groups(int g_l, int g_r, const SL& sl,
                              int16_t* __restrict__ lo, int16_t* __restrict__ hi,
                              int16_t* __restrict__ nxt, int16_t* __restrict__ prv,
                              int16_t* __restrict__ gf, int16_t* __restrict__ gl, int i,
-                             int W) {
+                             int W, const TieCtx& tc) {
     const int Ll = gl[g_l], Rf = gf[g_r], Rl = gl[g_r];
     if (Rf < 0) return;
     if (Ll < 0) {
@@ -145,7 +184,7 @@ __device__ void merge_groups(int g_l, int g_r, const SL& sl,
     bool left_alive = true, right_alive = true;
     for (;;) {
         const uint32_t A = sl.c(ia), B = sl.c(ib);
-        if (beats<kM>(B, A, i, sl.s(ia))) {  // A is hidden wherever it owned pixels
+        if (beats<kM>(B, A, i, sl.s(ia), tc)) {  // A is hidden wherever it owned pixels
             if (ia > lo[ca]) {
                 --ia;
                 continue;
@@ -166,7 +205,7 @@ __device__ void merge_groups(int g_l, int g_r, const SL& sl,
             const int cn = nxt[cb];
             bend = cn >= 0 ? sl.s(lo[cn]) : W;
         }
-        if (!beats<kM>(B, A, i, bend - 1)) {  // B is hidden wherever it owned pixels
+        if (!beats<kM>(B, A, i, bend - 1, tc)) {  // B is hidden wherever it owned pixels
             if (ib + 1 < hi[cb]) {
                 ++ib;
                 continue;
@@ -180,7 +219,7 @@ __device__ void merge_groups(int g_l, int g_r, const SL& sl,
             ib = lo[cb];
             continue;
         }
-        sl.s(ib) = (int16_t)first_win<kM>(A, B, i, W);  // the seam
+        sl.s(ib) = (int16_t)first_win<kM>(A, B, i, W, tc);  // the seam
         break;
     }
     if (left_alive && right_alive) {
@@ -248,7 +287,7 @@ __device__ __forceinline__ void store4(int32_t* __restrict__ p, int j, int W, bo
 // that a wavefront writes 1 KiB of contiguous output per instruction.
 template <int kM, int T>
 __device__ __forceinline__ void fill_row(const Img& g, int i, const uint32_t* cand,
-                                         const int16_t* st, int M, bool vec) {
+                                         const int16_t* st, int M, bool vec, const TieCtx& tc) {
     const int W = g.W;
     const int t = threadIdx.x;
     int32_t* drow = g.dist ? g.dist + (int64_t)i * g.opitch : nullptr;
@@ -278,7 +317,7 @@ __device__ __forceinline__ void fill_row(const Img& g, int i, const uint32_t* ca
                         nst = e + 1 < M ? st[e + 1] : INT32_MAX;
                     }
                     d[q] = dist_to<kM>(C, i, jj);
-                    f[q] = mul_c(crow(C), W) + ccol(C);
+                    f[q] = frow ? feature_of<kM>(C, i, d[q], W, tc) : 0;
                 } else {
                     d[q] = 0;
                     f[q] = 0;
@@ -321,6 +360,7 @@ __device__ void process_rows(const Img& g, int i0, int i1, int di,
     const int n = v.meta[0];
     const int W = g.W;
     if (!form_takes<T, S, kSparse, kGlobal>(n, W)) return;  // another form's image
+    const TieCtx tc{v.bits, v.down, W};
     const int pitch = v.meta[1];
     uint32_t* cand;
     int16_t* st;
@@ -374,12 +414,12 @@ __device__ void process_rows(const Img& g, int i0, int i1, int di,
             bool keep = true;
             while (m > 0) {
                 const uint32_t A = sl.c(base + m - 1);
-                if (beats<kM>(C, A, i, sl.s(base + m - 1))) {  // C hides the stack top
+                if (beats<kM>(C, A, i, sl.s(base + m - 1), tc)) {  // C hides the stack top
                     --m;
                     continue;
                 }
-                keep = beats<kM>(C, A, i, W - 1);  // C wins somewhere inside the row
-                if (keep) sl.s(base + m) = (int16_t)first_win<kM>(A, C, i, W);
+                keep = beats<kM>(C, A, i, W - 1, tc);  // C wins somewhere inside the row
+                if (keep) sl.s(base + m) = (int16_t)first_win<kM>(A, C, i, W, tc);
                 break;
             }
             if (m == 0) {
@@ -401,7 +441,8 @@ __device__ void process_rows(const Img& g, int i0, int i1, int di,
         // 3. merge up the tree
         for (int w = 1; w < nchunks; w <<= 1) {
             if ((t & (2 * w - 1)) == 0 && t + w < nchunks)
-                merge_groups<kM>(t, t + w, sl, sh.lo, sh.hi, sh.nxt, sh.prv, sh.gf, sh.gl, i, W);
+                merge_groups<kM>(t, t + w, sl, sh.lo, sh.hi, sh.nxt, sh.prv, sh.gf, sh.gl, i, W,
+                                 tc);
             __syncthreads();
         }
         // 4. survivors to the front of the list, in column order (plain layout)
@@ -439,7 +480,7 @@ __device__ void process_rows(const Img& g, int i0, int i1, int di,
         }
         __syncthreads();
         // 5. fill, four adjacent pixels per lane and step
-        fill_row<kM, T>(g, i, cand, st, M, vec);
+        fill_row<kM, T>(g, i, cand, st, M, vec, tc);
         __syncthreads();  // the next row reuses the list and the chunk tables
     }
 }
@@ -712,6 +753,7 @@ __global__ __launch_bounds__(T, T <= 512 ? 6 : 1) void k_row_segfill(Img g, SegB
     const int n = v.meta[0];
     const int W = g.W;
     if (n <= kSparseMaxN || W <= CAP / 2 || W > CAP) return;  // another form's image
+    const TieCtx tc{v.bits, v.down, W};
     const int pitch = v.meta[1];
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
     const int nchunks = (n + L - 1) / L;
@@ -759,7 +801,8 @@ __global__ __launch_bounds__(T, T <= 512 ? 6 : 1) void k_row_segfill(Img g, SegB
         __syncthreads();
         for (int w = 1; w < nchunks; w <<= 1) {
             if (t < nchunks && (t & (2 * w - 1)) == 0 && t + w < nchunks)
-                merge_groups<0>(t, t + w, sl, sh.lo, sh.hi, sh.nxt, sh.prv, sh.gf, sh.gl, i, W);
+                merge_groups<0>(t, t + w, sl, sh.lo, sh.hi, sh.nxt, sh.prv, sh.gf, sh.gl, i, W,
+                                tc);
             __syncthreads();
         }
         // survivors to the front, in column order
@@ -811,7 +854,7 @@ __global__ __launch_bounds__(T, T <= 512 ? 6 : 1) void k_row_segfill(Img g, SegB
             }
         }
         __syncthreads();
-        fill_row<0, T>(g, i, sh.cand, sh.st, M, vec);
+        fill_row<0, T>(g, i, sh.cand, sh.st, M, vec, tc);
         __syncthreads();  // the next row reuses the tables
     }
 }

@@ -74,8 +74,6 @@ def test_argument_validation_returns_before_any_launch(edt):
     assert lib.edt_sq(fake, 10, 10, 10, 2, 0, fake, 10, fake, ws, None) == -1
     assert lib.edt_sq(fake, 10, 10, 10, 0, 4, fake, 10, fake, ws, None) == -1  # past chamfer 4-3
     assert lib.edt_sq(fake, 10, 10, 10, 0, -1, fake, 10, fake, ws, None) == -1
-    # chessboard features are not provided
-    assert lib.edt_feature(fake, 10, 10, 10, 0, 2, fake, fake, 10, fake, ws, None) == -2
     assert lib.edt_sq(fake, 10, 10, 10, 0, 9, fake, 10, fake, ws, None) == -1
     # workspace: short, missing, misaligned
     assert lib.edt_sq(fake, 10, 10, 10, 0, 0, fake, 10, fake, ws - 1, None) == -1
@@ -111,7 +109,7 @@ def test_argument_validation_returns_before_any_launch(edt):
     assert lib.edt_feature_noalloc(None, 10, 10, 10, 0, 0, fake, fake, 10, None) == -1
     assert lib.edt_feature_noalloc(fake, 10, 10, 9, 0, 0, fake, fake, 10, None) == -1
     assert lib.edt_feature_noalloc(fake, 10, 10, 10, 3, 0, fake, fake, 10, None) == -1
-    assert lib.edt_feature_noalloc(fake, 10, 10, 10, 0, 2, fake, fake, 10, None) == -2
+    assert lib.edt_feature_noalloc(fake, 10, 10, 10, 0, 4, fake, fake, 10, None) == -1
     # sqrt
     assert lib.edt_sqrt_f32(fake, fake, -1, None) == -1
     assert lib.edt_sqrt_f32(None, fake, 5, None) == -1

@@ -1,7 +1,8 @@
 """City-block, chessboard and chamfer 4-3 transforms on the GPU (edt_sq /
-edt_feature with EDT_METRIC_CITYBLOCK, _CHESSBOARD and _CHAMFER34): bit-exact
-with the oracle's definition (O1) and, for city-block and chamfer 4-3, with
-the propagation scans of Sections 2.1 and 2.2."""
+edt_feature with EDT_METRIC_CITYBLOCK, _CHESSBOARD and _CHAMFER34): distances
+and features (smallest index among the nearest sites) bit-exact with the
+oracle's definition (O1) and, for city-block and chamfer 4-3, with the
+propagation scans of Sections 2.1 and 2.2."""
 import numpy as np
 import pytest
 
@@ -51,36 +52,35 @@ def test_metric_matches_definition(edt, metric, k):
     name, m = MASKS[k]
     for pol in (0, 1):
         sites = int((m != 0).sum()) if pol == 0 else int((m == 0).sum())
-        D, F = _run(edt, m, pol, metric, feature=(metric != 2))
+        D, F = _run(edt, m, pol, metric, feature=True)
         # the definition is quadratic: where it would take long (inverted
         # polarity of large masks) the raster scans stand in for city-block
         # and chamfer, and chessboard is left to the smaller masks
         if sites * m.size <= 2e9:
             Db, Fb = oracle.brute_metric(m, metric, pol)
             assert np.array_equal(D, Db), (name, pol)
-            if metric != 2:
-                assert np.array_equal(F, Fb), (name, pol)
+            assert np.array_equal(F, Fb), (name, pol)
         else:
             # the definition at sampled pixels (smallest index among equals)
             rng = np.random.default_rng(2106303 + metric)
             lin = rng.choice(m.size, size=min(m.size, int(2e9 // sites)), replace=False)
             Db, Fb = oracle.brute_metric_at(m, metric, lin, pol)
             assert np.array_equal(D.reshape(-1)[lin], Db), (name, pol)
-            if metric != 2:
-                assert np.array_equal(F.reshape(-1)[lin], Fb), (name, pol)
+            assert np.array_equal(F.reshape(-1)[lin], Fb), (name, pol)
         if metric == 1:
             assert np.array_equal(D, oracle.cityblock_scans(m, pol)), (name, pol)
         if metric == 3:
             assert np.array_equal(D, oracle.chamfer_scans(m, pol)), (name, pol)
             assert np.array_equal(_run(edt, m, pol, metric, feature=False)[0], D), (name, pol)
-        if metric != 2 and sites:
+        if sites:
             # every feature is a site at the reported distance
             H, W = m.shape
             r, c = F // W, F % W
             site = (m != 0) if pol == 0 else (m == 0)
             assert site[r, c].all(), (name, pol)
             di, dj = np.abs(np.indices((H, W))[0] - r), np.abs(np.indices((H, W))[1] - c)
-            want = di + dj if metric == 1 else 3 * np.maximum(di, dj) + np.minimum(di, dj)
+            want = (di + dj if metric == 1 else np.maximum(di, dj) if metric == 2 else
+                    3 * np.maximum(di, dj) + np.minimum(di, dj))
             assert np.array_equal(D, want), (name, pol)
 
 
@@ -111,9 +111,6 @@ def test_metric_errors(edt):
     import torch
     mt = torch.zeros((8, 8), dtype=torch.uint8, device="cuda:0")
     with pytest.raises(edt.EDTError) as e:
-        edt.feature(mt, metric=2)  # chessboard features: not decided by the vertical pass
-    assert e.value.status == -2
-    with pytest.raises(edt.EDTError) as e:
         edt.sq(mt, metric=4)
     assert e.value.status == -1
 
@@ -124,7 +121,35 @@ def test_wide_rows_chessboard_cityblock_chamfer(edt):
     m = (rng.random((6, 20000)) < 0.002).astype(np.uint8)
     for metric in (1, 2, 3):
         Db, Fb = oracle.brute_metric(m, metric, 0)
-        D, F = _run(edt, m, 0, metric, feature=(metric != 2))
+        D, F = _run(edt, m, 0, metric, feature=True)
         assert np.array_equal(D, Db)
-        if metric != 2:
-            assert np.array_equal(F, Fb)
+        assert np.array_equal(F, Fb)
+
+
+@pytest.mark.parametrize("pol", [0, 1])
+def test_chessboard_features_where_ties_sit_above_the_nearest_site(edt, pol):
+    """Chessboard ties whose smallest index is a site of a column above that
+    column's nearest site: a column with sites at rows i - 3 and i + 1 seen
+    from three columns away; regular grids and sparse sites in tall and wide
+    images (every row form, the global-slot form included)."""
+    m = np.zeros((40, 60), np.uint8)
+    m[10, 30] = m[14, 30] = 1          # column 30: sites 4 rows apart
+    m[5, 50] = m[25, 50] = m[26, 52] = 1
+    cases = [m]
+    g = np.zeros((64, 96), np.uint8)
+    g[::5, ::3] = 1
+    cases.append(g)
+    rng = np.random.default_rng(2106304 + pol)
+    for H, W, p in [(200, 1300, 0.002), (70, 3000, 0.02), (5, 17000, 0.001), (300, 90, 0.01)]:
+        cases.append((rng.random((H, W)) < p).astype(np.uint8))
+    for m in cases:
+        D, F = _run(edt, m, pol, 2, feature=True)
+        sites = int((m != 0).sum()) if pol == 0 else int((m == 0).sum())
+        if sites * m.size <= 2e9:
+            Db, Fb = oracle.brute_metric(m, 2, pol)
+            assert np.array_equal(D, Db) and np.array_equal(F, Fb), (m.shape, pol)
+        else:
+            lin = np.random.default_rng(7).choice(m.size, size=int(2e9 // sites), replace=False)
+            Db, Fb = oracle.brute_metric_at(m, 2, lin, pol)
+            assert np.array_equal(D.reshape(-1)[lin], Db), (m.shape, pol)
+            assert np.array_equal(F.reshape(-1)[lin], Fb), (m.shape, pol)

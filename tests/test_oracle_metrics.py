@@ -94,6 +94,33 @@ def test_metric_closed_forms_and_invariants(metric):
     assert (D2 <= D1).all() and (D1 <= 2 * D2).all()
 
 
+@pytest.mark.parametrize("pol", [0, 1])
+def test_chessboard_feature_is_the_squares_topmost_leftmost_site(pol):
+    """Under the chessboard metric every site of the square of half-side D
+    around a pixel lies at distance exactly D (D being the smallest distance),
+    so the nearest site with the smallest index is the square's topmost site,
+    leftmost among those: a characterisation by slicing, checked against the
+    oracle's features (smallest index among the nearest)."""
+    rng = np.random.default_rng(2106311 + pol)
+    for H, W, p in [(17, 29, 0.03), (23, 11, 0.1), (31, 31, 0.01), (9, 40, 0.2)]:
+        m = (rng.random((H, W)) < p).astype(np.uint8)
+        site = (m != 0) if pol == 0 else (m == 0)
+        if not site.any():
+            continue
+        D, F = oracle.brute_metric(m, 2, pol)
+        for i in range(H):
+            for j in range(W):
+                d = int(D[i, j])
+                box = site[max(0, i - d):i + d + 1, max(0, j - d):j + d + 1]
+                rows = np.nonzero(box.any(axis=1))[0]
+                r = rows[0]
+                c = np.nonzero(box[r])[0][0]
+                assert F[i, j] == (max(0, i - d) + r) * W + max(0, j - d) + c, (i, j)
+                # and no site lies strictly inside the square
+                inner = site[max(0, i - d + 1):i + d, max(0, j - d + 1):j + d]
+                assert not inner.any()
+
+
 # ---------------------------------------------------------------- chamfer 4-3
 
 def _float_table(name):
