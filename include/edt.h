@@ -50,7 +50,7 @@
 extern "C" {
 #endif
 
-#define EDT_ABI_VERSION 1
+#define EDT_ABI_VERSION 2
 
 typedef int32_t edt_status;
 #define EDT_OK 0
@@ -245,36 +245,49 @@ edt_status edt_batch_submit(edt_plan *plan, const uint8_t *mask_base, int32_t *d
                             int32_t *feat_base, void *workspace, size_t workspace_bytes,
                             void *stream);
 
-/* Result of edt_batch_autotune (host struct). */
-#define EDT_TUNE_MAX 8
+/* How a batch is laid out on the GPU (host struct).  Results never depend on
+ * it. */
 typedef struct {
-    int32_t tried;                       /* candidate schedules timed */
-    int32_t chosen;                      /* index of the one kept */
-    int32_t lane_w[EDT_TUNE_MAX];        /* widest image rowed one lane per row */
-    int32_t largest_first[EDT_TUNE_MAX]; /* images listed by decreasing size */
-    float ms[EDT_TUNE_MAX];              /* best of three timed submissions */
+    int32_t lane_w;        /* widest image given the one-lane-per-row row pass,
+                              0..1024 (that pass also takes only images of at
+                              most 4096 rows) */
+    int32_t largest_first; /* != 0: images listed by decreasing width, then
+                              height, so that the longest work items start first */
+    int32_t branches;      /* 1, or 2: the images split into two halves of about
+                              equal area, each with its own table and launches,
+                              the two launch sequences running side by side
+                              (two branches of the captured graph) */
+    int32_t wide_single;   /* != 0: images wider than 1024 columns run as single
+                              transforms (the segment path of edt_feature) instead
+                              of in the batch's row forms */
+} edt_schedule;
+
+/* Result of edt_batch_autotune (host struct). */
+#define EDT_TUNE_MAX 24
+typedef struct {
+    int32_t tried;                   /* candidate schedules timed */
+    int32_t chosen;                  /* index of the one kept */
+    edt_schedule cand[EDT_TUNE_MAX]; /* the candidates, in the order timed */
+    float ms[EDT_TUNE_MAX];          /* best of three timed submissions */
 } edt_tune_report;
 
 /* Autotune the plan's schedule on these buffers (same arguments as
  * edt_batch_submit; the outputs are written, with the same values, by every
- * candidate).  Candidates: which widths take the one-lane-per-row row pass
- * (none, up to 256, up to 1024, as the batch's widths make them differ) and
- * whether images are listed largest first, so that the longest work items
- * start first.  Each is run once untimed and three times timed with HIP events
- * on `stream` (this call waits for them); the fastest is kept for later
- * submissions.  report (host) may be NULL.  Results never depend on the
- * schedule. */
+ * candidate).  Candidates: every combination of lane_w (0, 256, 1024, as the
+ * batch's widths make them differ), largest_first (0, 1), branches (1, 2)
+ * and, if some image is wider than 1024 columns, wide_single (0, 1).  Each is
+ * run once untimed and three times timed with HIP events on `stream` (this
+ * call waits for them); the fastest is kept for later submissions.  report
+ * (host) may be NULL. */
 edt_status edt_batch_autotune(edt_plan *plan, const uint8_t *mask_base, int32_t *dist_base,
                               int32_t *feat_base, void *workspace, size_t workspace_bytes,
                               void *stream, edt_tune_report *report);
 
-/* Use the schedule (lane_w = widest image given the one-lane-per-row row
- * pass, 0..1024, which also takes only images of at most 4096 rows;
- * largest_first != 0: images listed by decreasing size) for
- * later submissions, e.g. one that edt_batch_autotune picked for batches of
- * the same shapes.  Errors: EDT_ERR_INVALID_ARG, EDT_ERR_OUT_OF_MEMORY,
+/* Use the schedule *s (host) for later submissions, e.g. one that
+ * edt_batch_autotune picked for batches of the same shapes.  Errors:
+ * EDT_ERR_INVALID_ARG (a field out of range), EDT_ERR_OUT_OF_MEMORY,
  * EDT_ERR_DEVICE. */
-edt_status edt_batch_set_schedule(edt_plan *plan, int32_t lane_w, int32_t largest_first);
+edt_status edt_batch_set_schedule(edt_plan *plan, const edt_schedule *s);
 
 /* Release a plan (its device tables and graphs).  Work already enqueued with
  * it must have completed. */

@@ -264,17 +264,24 @@ class ImageDesc(ctypes.Structure):
                 ("polarity", ctypes.c_int32), ("want_feature", ctypes.c_int32)]
 
 
+class Schedule(ctypes.Structure):
+    _fields_ = [("lane_w", ctypes.c_int32), ("largest_first", ctypes.c_int32),
+                ("branches", ctypes.c_int32), ("wide_single", ctypes.c_int32)]
+
+
+EDT_TUNE_MAX = 24
+
+
 class TuneReport(ctypes.Structure):
     _fields_ = [("tried", ctypes.c_int32), ("chosen", ctypes.c_int32),
-                ("lane_w", ctypes.c_int32 * 8), ("largest_first", ctypes.c_int32 * 8),
-                ("ms", ctypes.c_float * 8)]
+                ("cand", Schedule * EDT_TUNE_MAX), ("ms", ctypes.c_float * EDT_TUNE_MAX)]
 
 
 def _bind_batch():
     P, i32, sz = ctypes.c_void_p, ctypes.c_int32, ctypes.c_size_t
     _lib.edt_batch_autotune.argtypes = [P, P, P, P, P, sz, P, P]
     _lib.edt_batch_autotune.restype = i32
-    _lib.edt_batch_set_schedule.argtypes = [P, i32, i32]
+    _lib.edt_batch_set_schedule.argtypes = [P, P]
     _lib.edt_batch_set_schedule.restype = i32
     _lib.edt_batch_plan.argtypes = [P, i32, i32, P, P]
     _lib.edt_batch_plan.restype = i32
@@ -369,13 +376,16 @@ class BatchPlan:
                                        workspace.numel() * workspace.element_size(),
                                        _stream_ptr(stream), ctypes.byref(rep)),
                "edt_batch_autotune")
-        cands = [{"lane_w": rep.lane_w[q], "largest_first": bool(rep.largest_first[q]),
+        cands = [{"lane_w": rep.cand[q].lane_w, "largest_first": bool(rep.cand[q].largest_first),
+                  "branches": rep.cand[q].branches, "wide_single": bool(rep.cand[q].wide_single),
                   "ms": round(float(rep.ms[q]), 4)} for q in range(rep.tried)]
         return cands, int(rep.chosen)
 
-    def set_schedule(self, lane_w: int, largest_first: bool):
+    def set_schedule(self, lane_w: int, largest_first: bool, branches: int = 1,
+                     wide_single: bool = False):
         """Use a known schedule (e.g. one autotune picked) for later submissions."""
-        _check(_lib.edt_batch_set_schedule(self._plan, int(lane_w), int(largest_first)),
+        sc = Schedule(int(lane_w), int(largest_first), int(branches), int(wide_single))
+        _check(_lib.edt_batch_set_schedule(self._plan, ctypes.byref(sc)),
                "edt_batch_set_schedule")
 
     def close(self):

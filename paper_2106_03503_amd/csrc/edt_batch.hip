@@ -2,10 +2,14 @@
 // phase of the transform runs as one persistent launch over a device table of
 // the images, instead of one launch per phase per image, and a submission with
 // the same buffers as the previous one replays a captured HIP graph of those
-// launches.  How the work is laid out (which widths take the one-lane-per-row
-// row pass, and whether the images are listed largest first so that the
-// longest work items start first) is a schedule; edt_batch_autotune times the
-// candidate schedules on the caller's buffers and keeps the fastest.
+// launches.  How the work is laid out is a schedule: which widths take the
+// one-lane-per-row row pass, whether the images are listed largest first so
+// that the longest work items start first, whether the images are split into
+// two halves of about equal area whose launch sequences run side by side (two
+// branches of the graph, so that one half's tail overlaps the other's work),
+// and whether images wider than the lane pass run as single transforms (the
+// segment path) instead of in the batch's row forms.  edt_batch_autotune
+// times the candidate schedules on the caller's buffers and keeps the fastest.
 #include "../../include/edt.h"
 #include "edt_internal.h"
 
@@ -87,27 +91,38 @@ hipError_t enqueue_batch(const BatchTable& t, const int* totals, int max_w, hipS
 
 }  // namespace edt
 
-// One way of laying out a batch: the table, its work totals and the widest
-// image taking the several-lanes-per-row row pass.
-struct Schedule {
-    int lane_w = edt::kLaneMaxW;   // widest image taking the one-lane-per-row pass
-    bool largest_first = false;   // images listed by decreasing width, then height
-    void* table = nullptr;        // device copy of the batch table
+// One part of a batch under a schedule: a table over some of its images, its
+// work totals and the widest image taking the several-lanes-per-row row pass.
+struct Part {
+    void* table = nullptr;  // device copy of the table
+    int nimg = 0;
     int totals[edt::kPhases] = {};
     int max_w = 0;
+};
+
+// One way of laying out a batch: one or two parts (launched side by side),
+// and the images run as single transforms.
+struct Schedule {
+    edt_schedule knobs = {edt::kLaneMaxW, 0, 1, 0};
+    std::vector<Part> parts;
+    std::vector<int> singles;  // plan image indices run through the single-image path
 };
 
 struct edt_plan {
     int nimg = 0;
     int want_dist = 1;
     int any_feat = 0;
+    int widest = 0;
     size_t ws_bytes = 0;
     int device = 0;
     std::vector<edt::BatchImage> img;  // host rows, in the order given
     std::vector<Schedule> sched;       // built so far
     int chosen = 0;
+    // the second launch sequence of two-part schedules, joined by events
+    hipStream_t aux = nullptr;
+    hipEvent_t fork = nullptr, join = nullptr;
     // captured launches for one set of buffers
-    hipStream_t cap_stream = nullptr;
+    hipStream_t cap_stream = nullptr, cap_aux = nullptr;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     const void* key[4] = {nullptr, nullptr, nullptr, nullptr};
@@ -117,6 +132,15 @@ struct edt_plan {
 
 namespace {
 
+bool same_knobs(const edt_schedule& a, const edt_schedule& b) {
+    return a.lane_w == b.lane_w && (a.largest_first != 0) == (b.largest_first != 0) &&
+           a.branches == b.branches && (a.wide_single != 0) == (b.wide_single != 0);
+}
+
+bool valid_knobs(const edt_schedule& k) {
+    return k.lane_w >= 0 && k.lane_w <= edt::kLaneMaxW && (k.branches == 1 || k.branches == 2);
+}
+
 void drop_graph(edt_plan* p) {
     if (p->exec) (void)hipGraphExecDestroy(p->exec);
     if (p->graph) (void)hipGraphDestroy(p->graph);
@@ -125,39 +149,129 @@ void drop_graph(edt_plan* p) {
     for (auto& k : p->key) k = nullptr;
 }
 
-// Build (table on the device) the schedule (lane_w, largest_first).
-edt_status make_schedule(edt_plan* p, int lane_w, bool largest_first, Schedule* out) {
-    const int n = p->nimg;
-    std::vector<edt::BatchImage> rows = p->img;
-    if (largest_first) {
-        std::stable_sort(rows.begin(), rows.end(), [](const edt::BatchImage& a,
-                                                      const edt::BatchImage& b) {
-            return a.W != b.W ? a.W > b.W : a.H > b.H;
-        });
-    }
+void free_schedule(Schedule& sc) {
+    for (auto& pt : sc.parts)
+        if (pt.table) (void)hipFree(pt.table);
+    sc.parts.clear();
+}
+
+edt_status make_part(const std::vector<edt::BatchImage>& rows, int lane_w, Part* out) {
+    const int n = (int)rows.size();
     std::vector<uint8_t> host(edt::table_bytes(n));
-    Schedule sc;
-    sc.lane_w = lane_w;
-    sc.largest_first = largest_first;
-    const edt_status st = edt::pack_table(rows.data(), n, lane_w, host.data(), sc.totals, &sc.max_w);
+    Part pt;
+    pt.nimg = n;
+    const edt_status st = edt::pack_table(rows.data(), n, lane_w, host.data(), pt.totals, &pt.max_w);
     if (st != EDT_OK) return st;
-    if (hipMalloc(&sc.table, host.size()) != hipSuccess) return EDT_ERR_OUT_OF_MEMORY;
-    if (hipMemcpy(sc.table, host.data(), host.size(), hipMemcpyHostToDevice) != hipSuccess) {
-        (void)hipFree(sc.table);
+    if (hipMalloc(&pt.table, host.size()) != hipSuccess) return EDT_ERR_OUT_OF_MEMORY;
+    if (hipMemcpy(pt.table, host.data(), host.size(), hipMemcpyHostToDevice) != hipSuccess) {
+        (void)hipFree(pt.table);
         return EDT_ERR_DEVICE;
     }
-    *out = sc;
+    *out = pt;
     return EDT_OK;
 }
 
-hipError_t enqueue(edt_plan* p, const Schedule& sc, const uint8_t* mask_base, int32_t* dist_base,
-                   int32_t* feat_base, void* workspace, hipStream_t s) {
-    edt::BatchTable t = edt::table_view(static_cast<const uint8_t*>(sc.table), p->nimg, sc.totals);
+// Build the schedule with these knobs (tables on the device).
+edt_status make_schedule(edt_plan* p, const edt_schedule& knobs, Schedule* out) {
+    Schedule sc;
+    sc.knobs = knobs;
+    std::vector<int> order;
+    for (int q = 0; q < p->nimg; ++q) {
+        if (knobs.wide_single && p->img[q].W > edt::kLaneMaxW)
+            sc.singles.push_back(q);
+        else
+            order.push_back(q);
+    }
+    auto bigger = [&](int a, int b) {
+        const edt::BatchImage &x = p->img[a], &y = p->img[b];
+        return x.W != y.W ? x.W > y.W : x.H > y.H;
+    };
+    if (knobs.largest_first) std::stable_sort(order.begin(), order.end(), bigger);
+    // two parts of about equal area: each image (largest area first) joins the
+    // part with less so far; each part keeps the schedule's order
+    std::vector<std::vector<int>> part_idx(knobs.branches == 2 ? 2 : 1);
+    if (part_idx.size() == 1 || order.size() < 2) {
+        part_idx.assign(1, order);
+    } else {
+        std::vector<int> by_area = order;
+        std::stable_sort(by_area.begin(), by_area.end(), [&](int a, int b) {
+            return (int64_t)p->img[a].H * p->img[a].W > (int64_t)p->img[b].H * p->img[b].W;
+        });
+        std::vector<char> side(p->nimg, 0);
+        int64_t area[2] = {0, 0};
+        for (int q : by_area) {
+            const int k = area[1] < area[0] ? 1 : 0;
+            side[q] = (char)k;
+            area[k] += (int64_t)p->img[q].H * p->img[q].W;
+        }
+        for (int q : order) part_idx[side[q]].push_back(q);
+    }
+    for (const auto& idx : part_idx) {
+        if (idx.empty()) continue;
+        std::vector<edt::BatchImage> rows;
+        rows.reserve(idx.size());
+        for (int q : idx) rows.push_back(p->img[q]);
+        Part pt;
+        const edt_status st = make_part(rows, knobs.lane_w, &pt);
+        if (st != EDT_OK) {
+            free_schedule(sc);
+            return st;
+        }
+        sc.parts.push_back(pt);
+    }
+    *out = std::move(sc);
+    return EDT_OK;
+}
+
+hipError_t enqueue_part(const edt_plan* p, const Part& pt, const uint8_t* mask_base,
+                        int32_t* dist_base, int32_t* feat_base, void* workspace, hipStream_t s) {
+    edt::BatchTable t = edt::table_view(static_cast<const uint8_t*>(pt.table), pt.nimg, pt.totals);
     t.mask_base = reinterpret_cast<uintptr_t>(mask_base);
     t.dist_base = p->want_dist ? reinterpret_cast<uintptr_t>(dist_base) : 0;
     t.feat_base = p->any_feat ? reinterpret_cast<uintptr_t>(feat_base) : 0;
     t.ws_base = reinterpret_cast<uintptr_t>(workspace);
-    return edt::enqueue_batch(t, sc.totals, sc.max_w, s);
+    return edt::enqueue_batch(t, pt.totals, pt.max_w, s);
+}
+
+hipError_t enqueue_single_image(const edt_plan* p, int q, const uint8_t* mask_base,
+                                int32_t* dist_base, int32_t* feat_base, void* workspace,
+                                hipStream_t s) {
+    const edt::BatchImage& b = p->img[q];
+    edt::Img g;
+    g.mask = mask_base + b.mask_off;
+    g.mpitch = b.mpitch;
+    g.dist = (b.outs & edt::kOutDist) ? dist_base + b.dist_off : nullptr;
+    g.feat = (b.outs & edt::kOutFeat) ? feat_base + b.feat_off : nullptr;
+    g.opitch = b.opitch;
+    g.ws = static_cast<uint8_t*>(workspace) + b.ws_off;
+    g.H = b.H;
+    g.W = b.W;
+    g.pol = b.pol;
+    g.metric = EDT_METRIC_EUCLIDEAN_SQ;
+    return edt::enqueue_single(g, s);
+}
+
+// The schedule's launches on s; a second part runs on aux, forked from and
+// joined back into s with events (inside a capture, aux joins the capture).
+hipError_t enqueue(edt_plan* p, const Schedule& sc, const uint8_t* mask_base, int32_t* dist_base,
+                   int32_t* feat_base, void* workspace, hipStream_t s, hipStream_t aux) {
+    const bool two = sc.parts.size() == 2;
+    hipError_t e = hipSuccess;
+    if (two) {
+        e = hipEventRecord(p->fork, s);
+        if (e == hipSuccess) e = hipStreamWaitEvent(aux, p->fork, 0);
+    }
+    for (size_t k = 0; k < sc.parts.size() && e == hipSuccess; ++k)
+        e = enqueue_part(p, sc.parts[k], mask_base, dist_base, feat_base, workspace,
+                         k == 1 ? aux : s);
+    for (size_t k = 0; k < sc.singles.size() && e == hipSuccess; ++k)
+        e = enqueue_single_image(p, sc.singles[k], mask_base, dist_base, feat_base, workspace,
+                                 two && (k & 1) ? aux : s);
+    if (two && e == hipSuccess) {
+        e = hipEventRecord(p->join, aux);
+        if (e == hipSuccess) e = hipStreamWaitEvent(s, p->join, 0);
+    }
+    return e;
 }
 
 edt_status check_buffers(edt_plan* p, const uint8_t* mask_base, int32_t* dist_base,
@@ -169,6 +283,17 @@ edt_status check_buffers(edt_plan* p, const uint8_t* mask_base, int32_t* dist_ba
     if (workspace_bytes < p->ws_bytes || (reinterpret_cast<uintptr_t>(workspace) & 255) != 0)
         return EDT_ERR_INVALID_ARG;
     return EDT_OK;
+}
+
+// Index of the schedule with these knobs, built if needed (-1 on error, *st set).
+int find_or_make(edt_plan* p, const edt_schedule& knobs, edt_status* st) {
+    for (size_t q = 0; q < p->sched.size(); ++q)
+        if (same_knobs(p->sched[q].knobs, knobs)) return (int)q;
+    Schedule sc;
+    *st = make_schedule(p, knobs, &sc);
+    if (*st != EDT_OK) return -1;
+    p->sched.push_back(std::move(sc));
+    return (int)p->sched.size() - 1;
 }
 
 }  // namespace
@@ -208,7 +333,9 @@ edt_status edt_batch_plan(const edt_image_desc* images, int32_t n, int32_t want_
         b.pol = d.polarity;
         b.outs = (want_dist ? edt::kOutDist : 0) | (d.want_feature ? edt::kOutFeat : 0);
         any_feat |= d.want_feature != 0;
-        ws += edt::layout_for(d.H, d.W, false).total;
+        // images wider than the lane pass may run as single transforms, whose
+        // workspace adds the segment buffers and row slots
+        ws += edt::layout_for(d.H, d.W, d.W > edt::kLaneMaxW).total;
     }
     {  // every candidate schedule must fit int32 totals: check the default
         std::vector<uint8_t> host(edt::table_bytes(n));
@@ -223,16 +350,21 @@ edt_status edt_batch_plan(const edt_image_desc* images, int32_t n, int32_t want_
     pl->want_dist = want_dist != 0;
     pl->any_feat = any_feat;
     pl->ws_bytes = ws;
+    for (const auto& b : img) pl->widest = b.W > pl->widest ? b.W : pl->widest;
     pl->img = std::move(img);
     pl->use_graph = std::getenv("EDT_NO_GRAPH") == nullptr;
     Schedule sc;
     edt_status st = hipGetDevice(&pl->device) == hipSuccess ? EDT_OK : EDT_ERR_DEVICE;
-    if (st == EDT_OK) st = make_schedule(pl, edt::kLaneMaxW, false, &sc);
-    if (st == EDT_OK) pl->sched.push_back(sc);
-    if (st == EDT_OK && hipEventCreateWithFlags(&pl->done, hipEventDisableTiming) != hipSuccess)
+    if (st == EDT_OK) st = make_schedule(pl, edt_schedule{edt::kLaneMaxW, 0, 1, 0}, &sc);
+    if (st == EDT_OK) pl->sched.push_back(std::move(sc));
+    if (st == EDT_OK && (hipEventCreateWithFlags(&pl->done, hipEventDisableTiming) != hipSuccess ||
+                         hipEventCreateWithFlags(&pl->fork, hipEventDisableTiming) != hipSuccess ||
+                         hipEventCreateWithFlags(&pl->join, hipEventDisableTiming) != hipSuccess ||
+                         hipStreamCreateWithFlags(&pl->aux, hipStreamNonBlocking) != hipSuccess))
         st = EDT_ERR_DEVICE;
     if (st == EDT_OK && pl->use_graph &&
-        hipStreamCreateWithFlags(&pl->cap_stream, hipStreamNonBlocking) != hipSuccess)
+        (hipStreamCreateWithFlags(&pl->cap_stream, hipStreamNonBlocking) != hipSuccess ||
+         hipStreamCreateWithFlags(&pl->cap_aux, hipStreamNonBlocking) != hipSuccess))
         st = EDT_ERR_DEVICE;
     if (st != EDT_OK) {
         edt_plan_destroy(pl);
@@ -253,7 +385,7 @@ edt_status edt_batch_submit(edt_plan* p, const uint8_t* mask_base, int32_t* dist
     const Schedule& sc = p->sched[p->chosen];
     // Kernel timing needs the launches themselves, so it bypasses the graph.
     if (!p->use_graph || edt::prof_enabled()) {
-        if (enqueue(p, sc, mask_base, dist_base, feat_base, workspace, s) != hipSuccess)
+        if (enqueue(p, sc, mask_base, dist_base, feat_base, workspace, s, p->aux) != hipSuccess)
             return EDT_ERR_DEVICE;
         return hipEventRecord(p->done, s) == hipSuccess ? EDT_OK : EDT_ERR_DEVICE;
     }
@@ -266,7 +398,7 @@ edt_status edt_batch_submit(edt_plan* p, const uint8_t* mask_base, int32_t* dist
         if (hipStreamBeginCapture(p->cap_stream, hipStreamCaptureModeThreadLocal) != hipSuccess)
             return EDT_ERR_DEVICE;
         const hipError_t le = enqueue(p, sc, mask_base, dist_base, feat_base, workspace,
-                                      p->cap_stream);
+                                      p->cap_stream, p->cap_aux);
         hipGraph_t g = nullptr;
         const hipError_t ce = hipStreamEndCapture(p->cap_stream, &g);
         if (le != hipSuccess || ce != hipSuccess || !g) {
@@ -291,19 +423,20 @@ edt_status edt_batch_autotune(edt_plan* p, const uint8_t* mask_base, int32_t* di
                                         workspace_bytes);
     if (cs != EDT_OK) return cs;
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-    int widest = 0;
-    for (const auto& b : p->img) widest = b.W > widest ? b.W : widest;
     // candidate lane widths: none, then each width class up to kLaneMaxW that
     // changes which images take the lane pass
     std::vector<int> lane_ws = {0};
     for (int w : {256, edt::kLaneMaxW}) {
-        const int eff = w < widest ? w : widest;
+        const int eff = w < p->widest ? w : p->widest;
         if (eff > lane_ws.back()) lane_ws.push_back(w);
     }
-    struct Cand { int lane_w; bool largest; };
-    std::vector<Cand> cands;
-    for (int w : lane_ws)
-        for (bool lf : {false, true}) cands.push_back({w, lf});
+    std::vector<edt_schedule> cands;
+    for (int ws_ : {0, 1}) {
+        if (ws_ && p->widest <= edt::kLaneMaxW) continue;
+        for (int br : {1, 2})
+            for (int w : lane_ws)
+                for (int lf : {0, 1}) cands.push_back(edt_schedule{w, lf, br, ws_});
+    }
     if ((int)cands.size() > EDT_TUNE_MAX) cands.resize(EDT_TUNE_MAX);
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
@@ -316,22 +449,13 @@ edt_status edt_batch_autotune(edt_plan* p, const uint8_t* mask_base, int32_t* di
     edt_tune_report rep;
     memset(&rep, 0, sizeof(rep));
     for (size_t c = 0; c < cands.size() && st == EDT_OK; ++c) {
-        int k = -1;
-        for (size_t q = 0; q < p->sched.size(); ++q)
-            if (p->sched[q].lane_w == cands[c].lane_w &&
-                p->sched[q].largest_first == cands[c].largest)
-                k = (int)q;
-        if (k < 0) {
-            Schedule sc;
-            st = make_schedule(p, cands[c].lane_w, cands[c].largest, &sc);
-            if (st != EDT_OK) break;
-            p->sched.push_back(sc);
-            k = (int)p->sched.size() - 1;
-        }
+        const int k = find_or_make(p, cands[c], &st);
+        if (k < 0) break;
         float t_min = 0.f;
         for (int rep_i = 0; rep_i < 4 && st == EDT_OK; ++rep_i) {  // one warm-up, three timed
             if (hipEventRecord(e0, s) != hipSuccess ||
-                enqueue(p, p->sched[k], mask_base, dist_base, feat_base, workspace, s) != hipSuccess ||
+                enqueue(p, p->sched[k], mask_base, dist_base, feat_base, workspace, s, p->aux) !=
+                    hipSuccess ||
                 hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) {
                 st = EDT_ERR_DEVICE;
                 break;
@@ -341,8 +465,7 @@ edt_status edt_batch_autotune(edt_plan* p, const uint8_t* mask_base, int32_t* di
             if (rep_i > 0 && (rep_i == 1 || ms < t_min)) t_min = ms;
         }
         if (st != EDT_OK) break;
-        rep.lane_w[c] = cands[c].lane_w;
-        rep.largest_first[c] = cands[c].largest;
+        rep.cand[c] = cands[c];
         rep.ms[c] = t_min;
         rep.tried = (int32_t)c + 1;
         if (best_k < 0 || t_min < best) {
@@ -360,19 +483,11 @@ edt_status edt_batch_autotune(edt_plan* p, const uint8_t* mask_base, int32_t* di
     return EDT_OK;
 }
 
-edt_status edt_batch_set_schedule(edt_plan* p, int32_t lane_w, int32_t largest_first) {
-    if (!p || lane_w < 0 || lane_w > edt::kLaneMaxW) return EDT_ERR_INVALID_ARG;
-    const bool lf = largest_first != 0;
-    int k = -1;
-    for (size_t q = 0; q < p->sched.size(); ++q)
-        if (p->sched[q].lane_w == lane_w && p->sched[q].largest_first == lf) k = (int)q;
-    if (k < 0) {
-        Schedule sc;
-        const edt_status st = make_schedule(p, lane_w, lf, &sc);
-        if (st != EDT_OK) return st;
-        p->sched.push_back(sc);
-        k = (int)p->sched.size() - 1;
-    }
+edt_status edt_batch_set_schedule(edt_plan* p, const edt_schedule* knobs) {
+    if (!p || !knobs || !valid_knobs(*knobs)) return EDT_ERR_INVALID_ARG;
+    edt_status st = EDT_OK;
+    const int k = find_or_make(p, *knobs, &st);
+    if (k < 0) return st;
     if (p->chosen != k) drop_graph(p);
     p->chosen = k;
     return EDT_OK;
@@ -387,8 +502,13 @@ edt_status edt_plan_destroy(edt_plan* p) {
     }
     drop_graph(p);
     if (p->cap_stream) (void)hipStreamDestroy(p->cap_stream);
+    if (p->cap_aux) (void)hipStreamDestroy(p->cap_aux);
+    if (p->aux) (void)hipStreamDestroy(p->aux);
+    if (p->fork) (void)hipEventDestroy(p->fork);
+    if (p->join) (void)hipEventDestroy(p->join);
     for (auto& sc : p->sched)
-        if (sc.table && hipFree(sc.table) != hipSuccess) st = EDT_ERR_DEVICE;
+        for (auto& pt : sc.parts)
+            if (pt.table && hipFree(pt.table) != hipSuccess) st = EDT_ERR_DEVICE;
     delete p;
     return st;
 }

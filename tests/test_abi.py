@@ -37,7 +37,7 @@ def test_library_exports_every_declared_symbol(edt):
 
 def test_abi_version_and_status_strings(edt):
     from paper_2106_03503_amd import _lib
-    assert edt.abi_version() == 1
+    assert edt.abi_version() == 2
     for code, text in ((0, "ok"), (-1, "invalid argument"), (-2, "unsupported metric"),
                        (-3, "image too large"), (-7, "device error")):
         assert _lib.status_string(code) == text

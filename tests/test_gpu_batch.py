@@ -169,8 +169,12 @@ def test_autotune_keeps_results_and_picks_the_fastest(edt):
     D, F = plan.outputs(dev)
     ws = torch.empty(max(plan.workspace_bytes, 1), dtype=torch.uint8, device=dev)
     cands, chosen = plan.autotune(mask, D, F, workspace=ws)
-    assert len(cands) >= 4 and 0 <= chosen < len(cands)
+    # every combination of lane width, order, branches and the single path for
+    # the 1500-wide image
+    assert len(cands) == 24 and 0 <= chosen < len(cands)
     assert {c["lane_w"] for c in cands} >= {0, 256, 1024}
+    assert {c["branches"] for c in cands} == {1, 2}
+    assert {c["wide_single"] for c in cands} == {False, True}
     assert cands[chosen]["ms"] == min(c["ms"] for c in cands)
     for rep in range(2):  # the tuned schedule, replayed
         D.fill_(-9)
@@ -182,8 +186,9 @@ def test_autotune_keeps_results_and_picks_the_fastest(edt):
             assert np.array_equal(plan.image(D, q).cpu().numpy(), Do), (rep, q)
             if wf:
                 assert np.array_equal(plan.image(F, q).cpu().numpy(), Fo), (rep, q)
-    for lane_w, lf in ((0, True), (256, False)):  # schedules set by hand
-        plan.set_schedule(lane_w, lf)
+    for lane_w, lf, br, wsg in ((0, True, 1, False), (256, False, 2, False),
+                                (1024, True, 2, True), (1024, False, 1, True)):
+        plan.set_schedule(lane_w, lf, br, wsg)  # schedules set by hand
         D.fill_(-9)
         F.fill_(-9)
         plan.submit(mask, D, F, workspace=ws)
@@ -195,4 +200,6 @@ def test_autotune_keeps_results_and_picks_the_fastest(edt):
                 assert np.array_equal(plan.image(F, q).cpu().numpy(), Fo), (lane_w, q)
     with pytest.raises(edt.EDTError):
         plan.set_schedule(2048, False)
+    with pytest.raises(edt.EDTError):
+        plan.set_schedule(1024, False, branches=3)
     plan.close()
