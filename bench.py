@@ -415,10 +415,10 @@ def run_batch(args):
     tune = None
     if args.schedule:
         knobs = [int(x) for x in args.schedule.split(",")]
-        lw, lf, br, wsg = (knobs + [1, 1, 0][len(knobs) - 1:])[:4]
-        plan.set_schedule(lw, bool(lf), br, bool(wsg))
+        lw, lf, br, wsg, tr = (knobs + [1, 1, 0, 0][len(knobs) - 1:])[:5]
+        plan.set_schedule(lw, bool(lf), br, bool(wsg), bool(tr))
         tune = {"fixed": {"lane_w": lw, "largest_first": bool(lf), "branches": br,
-                          "wide_single": bool(wsg)}}
+                          "wide_single": bool(wsg), "transpose": bool(tr)}}
     elif not args.no_autotune:
         cands, chosen = plan.autotune(mask, D, F, workspace=ws, stream=stream)
         tune = {"candidates": cands, "chosen": chosen}
@@ -638,7 +638,7 @@ def main():
                     help="batch2048: keep the default schedule instead of autotuning it")
     ap.add_argument("--schedule", default="",
                     help="batch2048: use this schedule 'lane_w,largest_first[,branches"
-                         "[,wide_single]]' instead of autotuning (e.g. 1024,1,2)")
+                         "[,wide_single[,transpose]]]' instead of autotuning (e.g. 1024,1,2)")
     ap.add_argument("--capacity", action="store_true",
                     help="serve: also replay the requests all at once (the capacity)")
     ap.add_argument("--no-extras", action="store_true",

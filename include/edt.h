@@ -260,10 +260,16 @@ typedef struct {
     int32_t wide_single;   /* != 0: images wider than 1024 columns run as single
                               transforms (the segment path of edt_feature) instead
                               of in the batch's row forms */
+    int32_t transpose;     /* != 0: images wider than tall whose transpose takes
+                              the one-lane-per-row pass (H <= lane_w, W <= 4096)
+                              run as their transposes, the order of the two passes
+                              exchanged (Section 3.2.1): the mask is copied
+                              transposed into the workspace and the outputs
+                              copied back */
 } edt_schedule;
 
 /* Result of edt_batch_autotune (host struct). */
-#define EDT_TUNE_MAX 24
+#define EDT_TUNE_MAX 48
 typedef struct {
     int32_t tried;                   /* candidate schedules timed */
     int32_t chosen;                  /* index of the one kept */
@@ -274,8 +280,9 @@ typedef struct {
 /* Autotune the plan's schedule on these buffers (same arguments as
  * edt_batch_submit; the outputs are written, with the same values, by every
  * candidate).  Candidates: every combination of lane_w (0, 256, 1024, as the
- * batch's widths make them differ), largest_first (0, 1), branches (1, 2)
- * and, if some image is wider than 1024 columns, wide_single (0, 1).  Each is
+ * batch's widths make them differ), largest_first (0, 1), branches (1, 2),
+ * wide_single (0, 1) if some image is wider than 1024 columns, and
+ * transpose (0, 1) if some image could run transposed.  Each is
  * run once untimed and three times timed with HIP events on `stream` (this
  * call waits for them); the fastest is kept for later submissions.  report
  * (host) may be NULL. */

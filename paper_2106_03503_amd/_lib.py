@@ -266,10 +266,11 @@ class ImageDesc(ctypes.Structure):
 
 class Schedule(ctypes.Structure):
     _fields_ = [("lane_w", ctypes.c_int32), ("largest_first", ctypes.c_int32),
-                ("branches", ctypes.c_int32), ("wide_single", ctypes.c_int32)]
+                ("branches", ctypes.c_int32), ("wide_single", ctypes.c_int32),
+                ("transpose", ctypes.c_int32)]
 
 
-EDT_TUNE_MAX = 24
+EDT_TUNE_MAX = 48
 
 
 class TuneReport(ctypes.Structure):
@@ -378,13 +379,15 @@ class BatchPlan:
                "edt_batch_autotune")
         cands = [{"lane_w": rep.cand[q].lane_w, "largest_first": bool(rep.cand[q].largest_first),
                   "branches": rep.cand[q].branches, "wide_single": bool(rep.cand[q].wide_single),
+                  "transpose": bool(rep.cand[q].transpose),
                   "ms": round(float(rep.ms[q]), 4)} for q in range(rep.tried)]
         return cands, int(rep.chosen)
 
     def set_schedule(self, lane_w: int, largest_first: bool, branches: int = 1,
-                     wide_single: bool = False):
+                     wide_single: bool = False, transpose: bool = False):
         """Use a known schedule (e.g. one autotune picked) for later submissions."""
-        sc = Schedule(int(lane_w), int(largest_first), int(branches), int(wide_single))
+        sc = Schedule(int(lane_w), int(largest_first), int(branches), int(wide_single),
+                      int(transpose))
         _check(_lib.edt_batch_set_schedule(self._plan, ctypes.byref(sc)),
                "edt_batch_set_schedule")
 

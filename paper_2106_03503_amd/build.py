@@ -25,7 +25,7 @@ CLANGXX = os.path.join(ROCM, "llvm", "bin", "clang++")
 
 SOURCES = ["edt_api.hip", "edt_column.hip", "edt_row.hip", "edt_batch.hip", "edt_profile.hip",
            "edt_serve.hip", "edt_row_lanes.hip", "edt_regions.hip",
-           "edt_danielsson.hip"]
+           "edt_danielsson.hip", "edt_transpose.hip"]
 
 HIP_FLAGS = [
     "--offload-arch=gfx950",

@@ -36,8 +36,9 @@ int32_t pack_table(const BatchImage* img, int n, int lane_w, uint8_t* dst, int* 
     for (int q = 0; q < n; ++q) {
         const int H = img[q].H, W = img[q].W;
         const bool lanes = W <= lane_w && H <= kLanePackMaxH;
+        const int tiles = img[q].tr ? items_tiles(W, H) : 0;  // original sides W x H
         const int64_t items[kPhases] = {items_bits(H, W), items_carry(H, W), 1, items_near(H, W),
-                                        lanes ? 0 : H, lanes ? items_lanes(H) : 0};
+                                        lanes ? 0 : H, lanes ? items_lanes(H) : 0, tiles, tiles};
         for (int p = 0; p < kPhases; ++p) {
             int32_t* pre = reinterpret_cast<int32_t*>(dst + img_bytes + p * pre_bytes);
             pre[q] = (int32_t)acc[p];
@@ -83,9 +84,12 @@ BatchTable table_view(const uint8_t* dev_table, int n, const int* totals) {
 }
 
 hipError_t enqueue_batch(const BatchTable& t, const int* totals, int max_w, hipStream_t s) {
-    hipError_t e = launch_column_pass_batch(t, totals, s);
+    hipError_t e = hipSuccess;
+    if (totals[kPhTrIn] > 0) e = launch_transpose_in(t, totals[kPhTrIn], s);
+    if (e == hipSuccess) e = launch_column_pass_batch(t, totals, s);
     if (e == hipSuccess && totals[kPhRows] > 0) e = launch_row_pass_batch(t, totals, max_w, s);
     if (e == hipSuccess && totals[kPhLanes] > 0) e = launch_row_lanes_batch(t, totals[kPhLanes], s);
+    if (e == hipSuccess && totals[kPhTrOut] > 0) e = launch_transpose_out(t, totals[kPhTrOut], s);
     return e;
 }
 
@@ -103,7 +107,7 @@ struct Part {
 // One way of laying out a batch: one or two parts (launched side by side),
 // and the images run as single transforms.
 struct Schedule {
-    edt_schedule knobs = {edt::kLaneMaxW, 0, 1, 0};
+    edt_schedule knobs = {edt::kLaneMaxW, 0, 1, 0, 0};
     std::vector<Part> parts;
     std::vector<int> singles;  // plan image indices run through the single-image path
 };
@@ -134,7 +138,14 @@ namespace {
 
 bool same_knobs(const edt_schedule& a, const edt_schedule& b) {
     return a.lane_w == b.lane_w && (a.largest_first != 0) == (b.largest_first != 0) &&
-           a.branches == b.branches && (a.wide_single != 0) == (b.wide_single != 0);
+           a.branches == b.branches && (a.wide_single != 0) == (b.wide_single != 0) &&
+           (a.transpose != 0) == (b.transpose != 0);
+}
+
+// An image the schedule processes as its transpose: wider than tall, and its
+// transpose (W rows of H columns) takes the one-lane-per-row row pass.
+bool transposes(const edt_schedule& k, const edt::BatchImage& b) {
+    return k.transpose && b.W > b.H && b.H <= k.lane_w && b.W <= edt::kLanePackMaxH;
 }
 
 bool valid_knobs(const edt_schedule& k) {
@@ -210,7 +221,14 @@ edt_status make_schedule(edt_plan* p, const edt_schedule& knobs, Schedule* out) 
         if (idx.empty()) continue;
         std::vector<edt::BatchImage> rows;
         rows.reserve(idx.size());
-        for (int q : idx) rows.push_back(p->img[q]);
+        for (int q : idx) {
+            edt::BatchImage b = p->img[q];
+            if (transposes(knobs, b)) {  // the table holds the transposed sides
+                std::swap(b.H, b.W);
+                b.tr = 1;
+            }
+            rows.push_back(b);
+        }
         Part pt;
         const edt_status st = make_part(rows, knobs.lane_w, &pt);
         if (st != EDT_OK) {
@@ -334,8 +352,15 @@ edt_status edt_batch_plan(const edt_image_desc* images, int32_t n, int32_t want_
         b.outs = (want_dist ? edt::kOutDist : 0) | (d.want_feature ? edt::kOutFeat : 0);
         any_feat |= d.want_feature != 0;
         // images wider than the lane pass may run as single transforms, whose
-        // workspace adds the segment buffers and row slots
-        ws += edt::layout_for(d.H, d.W, d.W > edt::kLaneMaxW).total;
+        // workspace adds the segment buffers and row slots; images wider than
+        // tall may run as their transposes, with transposed copies of the mask
+        // and outputs
+        size_t need = edt::layout_for(d.H, d.W, d.W > edt::kLaneMaxW).total;
+        if (d.W > d.H && d.H <= edt::kLaneMaxW && d.W <= edt::kLanePackMaxH)
+            need = std::max(need, edt::tr_layout(d.W, d.H).total);
+        b.tr = 0;
+        b.pad_ = 0;
+        ws += edt::align_up(need, 256);
     }
     {  // every candidate schedule must fit int32 totals: check the default
         std::vector<uint8_t> host(edt::table_bytes(n));
@@ -355,7 +380,7 @@ edt_status edt_batch_plan(const edt_image_desc* images, int32_t n, int32_t want_
     pl->use_graph = std::getenv("EDT_NO_GRAPH") == nullptr;
     Schedule sc;
     edt_status st = hipGetDevice(&pl->device) == hipSuccess ? EDT_OK : EDT_ERR_DEVICE;
-    if (st == EDT_OK) st = make_schedule(pl, edt_schedule{edt::kLaneMaxW, 0, 1, 0}, &sc);
+    if (st == EDT_OK) st = make_schedule(pl, edt_schedule{edt::kLaneMaxW, 0, 1, 0, 0}, &sc);
     if (st == EDT_OK) pl->sched.push_back(std::move(sc));
     if (st == EDT_OK && (hipEventCreateWithFlags(&pl->done, hipEventDisableTiming) != hipSuccess ||
                          hipEventCreateWithFlags(&pl->fork, hipEventDisableTiming) != hipSuccess ||
@@ -430,12 +455,21 @@ edt_status edt_batch_autotune(edt_plan* p, const uint8_t* mask_base, int32_t* di
         const int eff = w < p->widest ? w : p->widest;
         if (eff > lane_ws.back()) lane_ws.push_back(w);
     }
+    bool any_tr = false;  // some image is wider than tall and could run transposed
+    for (const auto& b : p->img)
+        any_tr |= transposes(edt_schedule{edt::kLaneMaxW, 0, 1, 0, 1}, b);
     std::vector<edt_schedule> cands;
-    for (int ws_ : {0, 1}) {
-        if (ws_ && p->widest <= edt::kLaneMaxW) continue;
-        for (int br : {1, 2})
-            for (int w : lane_ws)
-                for (int lf : {0, 1}) cands.push_back(edt_schedule{w, lf, br, ws_});
+    for (int tr : {0, 1}) {
+        if (tr && !any_tr) continue;
+        for (int ws_ : {0, 1}) {
+            if (ws_ && p->widest <= edt::kLaneMaxW) continue;
+            for (int br : {1, 2})
+                for (int w : lane_ws)
+                    for (int lf : {0, 1}) {
+                        if (tr && w == 0) continue;  // no image takes the lane pass
+                        cands.push_back(edt_schedule{w, lf, br, ws_, tr});
+                    }
+        }
     }
     if ((int)cands.size() > EDT_TUNE_MAX) cands.resize(EDT_TUNE_MAX);
     hipEvent_t e0 = nullptr, e1 = nullptr;

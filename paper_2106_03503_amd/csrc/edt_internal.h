@@ -111,6 +111,10 @@ struct Img {
     int H, W, pol;
     int metric;        // EDT_METRIC_*: 0 squared Euclidean, 1 city-block, 2 chessboard,
                        // 3 chamfer 4-3
+    int tr = 0;        // a batch image processed as its transpose: H, W, mask and
+                       // outputs are the transposed ones (in its workspace), ties in
+                       // the row pass go to the left column (the smaller original
+                       // row), and features are original indices
 };
 
 // Pointers into an image's workspace.
@@ -174,8 +178,16 @@ enum Phase {
     kPhNear = 3,
     kPhRows = 4,
     kPhLanes = 5,
-    kPhases = 6
+    kPhTrIn = 6,   // 64 x 64 tiles of the masks of transposed images
+    kPhTrOut = 7,  // 64 x 64 tiles of their outputs
+    kPhases = 8
 };
+
+// Tiles of kTrTile x kTrTile pixels of an H x W image (transposition).
+constexpr int kTrTile = 64;
+__host__ __device__ inline int items_tiles(int H, int W) {
+    return ((H + kTrTile - 1) / kTrTile) * ((W + kTrTile - 1) / kTrTile);
+}
 
 // One image of a batch, as offsets from the bases passed at submission (a
 // base may be 0, and the offsets then absolute addresses).
@@ -188,6 +200,9 @@ struct BatchImage {
     int64_t ws_off;    // bytes from the workspace base
     int32_t H, W, pol;
     int32_t outs;      // kOutDist | kOutFeat: the outputs this image writes
+    int32_t tr;        // processed as its transpose: H, W are the transposed sides,
+                       // the offsets and pitches the caller's
+    int32_t pad_;
 };
 constexpr int32_t kOutDist = 1;
 constexpr int32_t kOutFeat = 2;
@@ -260,6 +275,29 @@ __device__ __forceinline__ int64_t wave_uniform(int64_t x) {
     return (int64_t)(((uint64_t)hi << 32) | lo);
 }
 
+// Workspace of a batch image processed as its transpose (transposed sides
+// H x W): the transform's own layout, then the transposed mask (rows
+// align_up(W, 16) bytes apart) and the transposed outputs (rows align_up(W, 4)
+// elements apart), written back to the caller's outputs at the end.
+struct TrLayout {
+    size_t mask, dist, feat, total;
+    int64_t mpitch, opitch;
+};
+__host__ __device__ inline TrLayout tr_layout(int H, int W) {
+    TrLayout T;
+    T.mpitch = (int64_t)align_up((size_t)W, 16);
+    T.opitch = (int64_t)align_up((size_t)W, 4);
+    size_t off = align_up(layout_for(H, W, false).total, 256);
+    T.mask = off;
+    off = align_up(off + (size_t)H * T.mpitch, 256);
+    T.dist = off;
+    off = align_up(off + (size_t)H * T.opitch * 4, 256);
+    T.feat = off;
+    off = align_up(off + (size_t)H * T.opitch * 4, 256);
+    T.total = off;
+    return T;
+}
+
 // Image im of the batch; im is the same in every lane of the wavefront.
 __device__ inline Img batch_img(const BatchTable& t, int im) {
     const BatchImage b = t.img[im];
@@ -281,6 +319,16 @@ __device__ inline Img batch_img(const BatchTable& t, int im) {
     g.W = wave_uniform((int32_t)b.W);
     g.pol = wave_uniform((int32_t)b.pol);
     g.metric = 0;
+    g.tr = wave_uniform((int32_t)b.tr);
+    if (g.tr) {  // the transposed copies in the image's workspace
+        const TrLayout T = tr_layout(g.H, g.W);
+        const uintptr_t ws = t.ws_base + (uintptr_t)ws_off;
+        g.mask = global_ptr<const uint8_t>(ws + T.mask);
+        g.mpitch = T.mpitch;
+        g.dist = (outs & kOutDist) ? global_ptr<int32_t>(ws + T.dist) : nullptr;
+        g.feat = (outs & kOutFeat) ? global_ptr<int32_t>(ws + T.feat) : nullptr;
+        g.opitch = T.opitch;
+    }
     return g;
 }
 
@@ -355,6 +403,10 @@ hipError_t launch_column_pass_batch(const BatchTable& t, const int* totals, hipS
 hipError_t launch_row_pass_batch(const BatchTable& t, const int* totals, int max_w,
                                  hipStream_t stream);
 hipError_t launch_row_lanes_batch(const BatchTable& t, int total, hipStream_t stream);
+// Masks of the transposed images of a batch into their workspaces, and their
+// outputs back (totals: tiles of each phase).
+hipError_t launch_transpose_in(const BatchTable& t, int total, hipStream_t stream);
+hipError_t launch_transpose_out(const BatchTable& t, int total, hipStream_t stream);
 // Workspace of the segment path for dense rows of one image: per row the
 // envelope size of each segment, the envelopes themselves (entry e of segment
 // c at slot c kSegL + e of the row, packed candidate; its start at the same

@@ -175,7 +175,7 @@ template <bool kPk>
 __device__ __forceinline__ int scan_row(const int i, const int n, const int W,
                                         const int16_t* __restrict__ cols, int16_t* rr,
                                         uint32_t* sc, const bool vec, LaneRing<kPk>& ring,
-                                        const int lane) {
+                                        const int lane, const bool tl) {
     int M = 0, base = 0;
     int colA = 0, rowA = 0, gA = 0, sA = 0;  // top entry (M - 1)
     int dAs = 0, dAe = 0;  // the top's distances at its start sA and at pixel W - 1
@@ -209,7 +209,7 @@ __device__ __forceinline__ int scan_row(const int i, const int n, const int W,
                 // pop every parabola that the new one beats where it starts
                 while (M > 0) {
                     const int dC = gC + sqr_c(sA - col);
-                    if (!(dC < dAs || (dC == dAs && row < rowA))) break;
+                    if (!(dC < dAs || (dC == dAs && !tl && row < rowA))) break;
                     --M;
                     if (M > 0) {
                         if constexpr (kPk) {
@@ -237,8 +237,10 @@ __device__ __forceinline__ int scan_row(const int i, const int n, const int W,
                 }
                 int s = 0;
                 if (M > 0) {
-                    if (!(dCe < dAe || (dCe == dAe && row < rowA))) continue;  // never wins in the row
-                    s = first_after(gC - gA + mul_c(col - colA, col + colA) - (row < rowA ? 1 : 0),
+                    if (!(dCe < dAe || (dCe == dAe && !tl && row < rowA)))
+                        continue;  // never wins in the row
+                    s = first_after(gC - gA + mul_c(col - colA, col + colA) -
+                                        (!tl && row < rowA ? 1 : 0),
                                     2 * (col - colA), W);
                     if constexpr (kPk) {
                         cB = pk_entry(colA, sA, rowA);
@@ -298,7 +300,7 @@ __global__ __launch_bounds__(kLaneRows) void k_row_lanes_batch(BatchTable tb) {
         const int i = i0 + lane;
         s_m[lane] = scan_row<true>(i, n, W, v.cols, v.rc + (int64_t)i * pitch,
                                    reinterpret_cast<uint32_t*>(base + (int64_t)i * g.opitch), vec,
-                                   sh.ring, lane);
+                                   sh.ring, lane, g.tr != 0);
     }
     __syncthreads();  // stacks in memory are complete; the ring is free
 
@@ -360,7 +362,9 @@ __global__ __launch_bounds__(kLaneRows) void k_row_lanes_batch(BatchTable tb) {
                         }
                         const int col = pk_col(c), row = pk_row(c);
                         d[q] = sqr_c(i - row) + sqr_c(jj - col);
-                        f[q] = mul_c(row, W) + col;
+                        // a transposed image's site (row, col) is the
+                        // original pixel (col, row) of an image g.H wide
+                        f[q] = g.tr ? mul_c(col, g.H) + row : mul_c(row, W) + col;
                     }
                 }
             }
@@ -396,7 +400,8 @@ __global__ __launch_bounds__(kLaneRows) void k_row_segscan(Img g, SegBufs b) {
         if (i < g.H) {
             uint32_t* sc = b.env + (int64_t)i * pitch + q0;
             const int M = scan_row<false>(i, min(L, n - q0), g.W, v.cols + q0,
-                                          v.rc + (int64_t)i * pitch + q0, sc, true, ring, lane);
+                                          v.rc + (int64_t)i * pitch + q0, sc, true, ring, lane,
+                                          false);
             b.segm[(int64_t)i * seg_count(g.W) + y] = (int16_t)M;
             if (y == 0) b.rowfail[i] = 0;
         }

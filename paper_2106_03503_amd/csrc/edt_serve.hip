@@ -157,6 +157,8 @@ bool launch(edt_server* s, Group& g) {
         b.W = q.r.W;
         b.pol = q.r.polarity;
         b.outs = (q.r.dist_sq ? edt::kOutDist : 0) | (q.r.feature ? edt::kOutFeat : 0);
+        b.tr = 0;
+        b.pad_ = 0;
     }
     int totals[edt::kPhases], max_w = 0;
     uint8_t* host = s->staging[g.slot];

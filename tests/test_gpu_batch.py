@@ -40,10 +40,12 @@ def _images(seed, n, extra=()):
     return out
 
 
-def _check_batch(edt, imgs, want_dist=True, submits=2, fresh_buffers=False):
+def _check_batch(edt, imgs, want_dist=True, submits=2, fresh_buffers=False, schedule=None):
     import torch
     dev = torch.device("cuda:0")
     plan = edt.BatchPlan([(m.shape[0], m.shape[1], p, f) for m, p, f in imgs], want_dist=want_dist)
+    if schedule is not None:
+        plan.set_schedule(*schedule)
     mask = plan.pack([m for m, _, _ in imgs], dev)
     D, F = plan.outputs(dev)
     ws = None
@@ -169,12 +171,13 @@ def test_autotune_keeps_results_and_picks_the_fastest(edt):
     D, F = plan.outputs(dev)
     ws = torch.empty(max(plan.workspace_bytes, 1), dtype=torch.uint8, device=dev)
     cands, chosen = plan.autotune(mask, D, F, workspace=ws)
-    # every combination of lane width, order, branches and the single path for
-    # the 1500-wide image
-    assert len(cands) == 24 and 0 <= chosen < len(cands)
+    # every combination of lane width, order, branches, the single path for the
+    # 1500-wide image and the transposed order (not without the lane pass)
+    assert len(cands) == 40 and 0 <= chosen < len(cands)
     assert {c["lane_w"] for c in cands} >= {0, 256, 1024}
     assert {c["branches"] for c in cands} == {1, 2}
     assert {c["wide_single"] for c in cands} == {False, True}
+    assert {c["transpose"] for c in cands} == {False, True}
     assert cands[chosen]["ms"] == min(c["ms"] for c in cands)
     for rep in range(2):  # the tuned schedule, replayed
         D.fill_(-9)
@@ -186,9 +189,9 @@ def test_autotune_keeps_results_and_picks_the_fastest(edt):
             assert np.array_equal(plan.image(D, q).cpu().numpy(), Do), (rep, q)
             if wf:
                 assert np.array_equal(plan.image(F, q).cpu().numpy(), Fo), (rep, q)
-    for lane_w, lf, br, wsg in ((0, True, 1, False), (256, False, 2, False),
-                                (1024, True, 2, True), (1024, False, 1, True)):
-        plan.set_schedule(lane_w, lf, br, wsg)  # schedules set by hand
+    for lane_w, lf, br, wsg, tr in ((0, True, 1, False, False), (256, False, 2, False, True),
+                                    (1024, True, 2, True, True), (1024, False, 1, True, False)):
+        plan.set_schedule(lane_w, lf, br, wsg, tr)  # schedules set by hand
         D.fill_(-9)
         F.fill_(-9)
         plan.submit(mask, D, F, workspace=ws)
@@ -203,3 +206,35 @@ def test_autotune_keeps_results_and_picks_the_fastest(edt):
     with pytest.raises(edt.EDTError):
         plan.set_schedule(1024, False, branches=3)
     plan.close()
+
+
+def _wide_images(seed):
+    """Images wider than tall (and some taller, left as they are), with tie-heavy
+    grids: the transposed order breaks ties by the smaller original row first."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for (H, W) in [(1, 2), (1, 700), (3, 1024), (63, 64), (64, 65), (65, 1000), (100, 3000),
+                   (7, 4096), (300, 301), (1024, 1100), (200, 90), (40, 40)]:
+        for kind in range(3):
+            if kind == 0:
+                m = (rng.random((H, W)) < rng.uniform(0.001, 0.2)).astype(np.uint8)
+            elif kind == 1:
+                m = np.zeros((H, W), np.uint8)
+                m[::max(1, H // 5), ::3] = 1  # a grid: many equidistant sites
+            else:
+                m = workloads.ellipses(H, W, 6, 2, 40, rng=rng)
+            out.append((m, int(rng.integers(0, 2)), bool(rng.integers(0, 2)) or kind == 1))
+    return out
+
+
+@pytest.mark.parametrize("lane_w,branches", [(1024, 1), (256, 2)])
+def test_transposed_order_matches_oracle(edt, lane_w, branches):
+    # images wider than tall run as their transposes (Section 3.2.1), with
+    # graph replays; features are original indices with the smallest-index rule
+    _check_batch(edt, _wide_images(2106401), submits=2,
+                 schedule=(lane_w, True, branches, False, True))
+
+
+def test_transposed_order_features_only(edt):
+    imgs = [(m, pol, True) for m, pol, _ in _wide_images(2106402)[:18]]
+    _check_batch(edt, imgs, want_dist=False, submits=1, schedule=(1024, False, 1, False, True))
