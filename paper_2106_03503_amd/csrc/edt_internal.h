@@ -426,10 +426,10 @@ __host__ __device__ inline SegBufs seg_bufs(const Img& g) {
     return b;
 }
 // Dense rows of one image (has_segments(W), more than kSparseMaxN candidates,
-// known only on the device): envelopes of row segments of kSegL candidates,
-// one lane per (row, segment), to `b`; every row is marked as not left to the
-// merge.
-hipError_t launch_row_segscan(const Img& g, const SegBufs& b, hipStream_t stream);
+// known only on the device): envelopes of row segments of L candidates (kSegL
+// or 2 kSegL), one lane per (row, segment), to `b`, segment c's entries at
+// slots c L + e; every row is marked as not left to the merge.
+hipError_t launch_row_segscan(const Img& g, int L, const SegBufs& b, hipStream_t stream);
 hipError_t launch_sqrt(const int32_t* D, float* out, int64_t n, hipStream_t stream);
 
 }  // namespace edt

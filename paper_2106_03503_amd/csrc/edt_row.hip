@@ -506,29 +506,35 @@ __global__ __launch_bounds__(T) void k_row_single(Img g, uint8_t* __restrict__ s
 // that an equally near site with a smaller index is still seen); every
 // candidate beyond it is farther still.  A work item is one tile of kWinTile
 // pixels of a row; it copies into LDS the segments under the tile and
-// kWinHalo more on each side, and reads a segment beyond those from memory.
+// kWinHalo more on each side, and reads a segment beyond those from memory
+// (4096-pixel tiles with two more segments a side were the fastest of the
+// tile widths 1024..8192, halos 1..4 and 256..1024 lanes measured).
 // A row where some pixel would need more than kWinCap segments besides its
 // own is marked in rowfail and done by k_row_segfill instead: its segments
 // are merged up a binary tree (log2(n / L) levels), the survivors compacted,
 // and the row filled from them.
-constexpr int kWinTile = 2048;
+constexpr int kWinTile = 4096;
 constexpr int kWinLanes = 256;
-constexpr int kWinHalo = 4;
+constexpr int kWinHalo = 2;
 constexpr int kWinCap = 24;
-// segments a tile's columns can touch (each spans at least kSegL columns),
-// plus the halo
-constexpr int kWinSegs = kWinTile / kSegL + 1 + 2 * kWinHalo;
-constexpr int kMaxSegs = kLdsMaxW / kSegL;
-constexpr int kWinPer = (kWinSegs * kSegL + kWinLanes - 1) / kWinLanes;  // slots per lane
+// Segments of L candidates: those a tile's columns can touch (each spans at
+// least L columns), plus the halo, and the most a row can have.
+template <int L>
+struct WinShape {
+    static constexpr int kSegs = kWinTile / L + 1 + 2 * kWinHalo;
+    static constexpr int kMax = kLdsMaxW / L;
+    static constexpr int kPer = (kSegs * L + kWinLanes - 1) / kWinLanes;  // slots per lane
+};
 
+template <int L>
 struct WinLds {
-    uint32_t cand[kWinSegs * kSegL];
-    int16_t st[kWinSegs * kSegL];
-    int eleft[kWinSegs], eright[kWinSegs];   // envelope of each loaded segment at its
-                                             // first and last column
-    int16_t cnt[kWinSegs];                   // entries of each loaded segment
-    int16_t segof[kWinTile / 16];            // segment under every 16th pixel of the tile
-    int16_t first[kMaxSegs], last[kMaxSegs];  // columns of each segment's first and last candidate
+    static constexpr int S = WinShape<L>::kSegs, G = WinShape<L>::kMax;
+    uint32_t cand[S * L];
+    int16_t st[S * L];
+    int eleft[S], eright[S];   // envelope of each loaded segment at its first and last column
+    int16_t cnt[S];            // entries of each loaded segment
+    int16_t segof[kWinTile / 16];  // segment under every 16th pixel of the tile
+    int16_t first[G], last[G];     // columns of each segment's first and last candidate
 };
 
 // Last index e in [lo, hi) with st[e] <= j, given st[lo] <= j (LDS or memory).
@@ -579,15 +585,18 @@ __device__ __forceinline__ int seg_at(const int16_t* first, int nseg, int x) {
     return a;
 }
 
+template <int L>
 __global__ __launch_bounds__(kWinLanes) void k_row_segwin(Img g, SegBufs sb) {
-    __shared__ WinLds sh;
+    __shared__ WinLds<L> sh;
+    constexpr int kPer = WinShape<L>::kPer;
+    static_assert(L >= 16, "a 16-pixel step crosses at most one segment start");
     __shared__ int s_lo, s_hi;
     const Views v = views_of(g);
     const int n = v.meta[0];
     if (n <= kSparseMaxN) return;  // the one-wavefront row pass took the image
     const int W = g.W;
     const int pitch = v.meta[1];
-    const int nseg = (n + kSegL - 1) / kSegL;
+    const int nseg = (n + L - 1) / L;
     const int ntiles = (W + kWinTile - 1) / kWinTile;
     const int total = g.H * ntiles;
     const int t = threadIdx.x;
@@ -596,8 +605,8 @@ __global__ __launch_bounds__(kWinLanes) void k_row_segwin(Img g, SegBufs sb) {
                      (!g.feat || reinterpret_cast<uintptr_t>(g.feat) % 16 == 0) &&
                      (g.opitch % 4 == 0);
     for (int c = t; c < nseg; c += kWinLanes) {
-        sh.first[c] = v.cols[c * kSegL];
-        sh.last[c] = v.cols[min((c + 1) * kSegL, n) - 1];
+        sh.first[c] = v.cols[c * L];
+        sh.last[c] = v.cols[min((c + 1) * L, n) - 1];
     }
     for (int item = blockIdx.x; item < total; item += gridDim.x) {
         const int i = item / ntiles;
@@ -608,17 +617,17 @@ __global__ __launch_bounds__(kWinLanes) void k_row_segwin(Img g, SegBufs sb) {
             s_hi = min(nseg - 1, seg_at(sh.first, nseg, x1 - 1) + kWinHalo);
         }
         __syncthreads();
-        const int lo = s_lo, hi = s_hi;  // loaded segments [lo, hi], at most kWinSegs
+        const int lo = s_lo, hi = s_hi;  // loaded segments [lo, hi], at most WinShape<L>::kSegs
         const uint32_t* erow = sb.env + (int64_t)i * pitch;
         const int16_t* srow = v.rc + (int64_t)i * pitch;
         const int16_t* mrow = sb.segm + (int64_t)i * sstride;
         // every load in flight before the LDS writes: slots of candidates
         // past a segment's envelope are copied too and never read
-        const int q0 = lo * kSegL, qn = min(n, (hi + 1) * kSegL);
-        uint32_t vc[kWinPer];
-        int vs[kWinPer];
+        const int q0 = lo * L, qn = min(n, (hi + 1) * L);
+        uint32_t vc[kPer];
+        int vs[kPer];
 #pragma unroll
-        for (int u = 0; u < kWinPer; ++u) {
+        for (int u = 0; u < kPer; ++u) {
             const int q = q0 + t + u * kWinLanes;
             if (q < qn) {
                 vc[u] = erow[q];
@@ -628,7 +637,7 @@ __global__ __launch_bounds__(kWinLanes) void k_row_segwin(Img g, SegBufs sb) {
         const int mt = t <= hi - lo ? mrow[lo + t] : 0;
         if (t <= hi - lo) sh.cnt[t] = (int16_t)mt;
 #pragma unroll
-        for (int u = 0; u < kWinPer; ++u) {
+        for (int u = 0; u < kPer; ++u) {
             const int q = q0 + t + u * kWinLanes;
             if (q < qn) {
                 sh.cand[q - q0] = vc[u];
@@ -642,7 +651,7 @@ __global__ __launch_bounds__(kWinLanes) void k_row_segwin(Img g, SegBufs sb) {
         // column.  These two values bound a segment before it is searched.
         if (t < kWinTile / 16) sh.segof[t] = (int16_t)seg_at(sh.first, nseg, x0 + 16 * t);
         if (t <= hi - lo) {
-            const int b0 = t * kSegL, f = sh.first[lo + t], l = sh.last[lo + t];
+            const int b0 = t * L, f = sh.first[lo + t], l = sh.last[lo + t];
             const uint32_t Cf = sh.cand[last_le_any(sh.st, b0, b0 + mt, f)];
             const uint32_t Cl = sh.cand[last_le_any(sh.st, b0, b0 + mt, l)];
             sh.eleft[t] = sqr_c(i - crow(Cf)) + sqr_c(f - ccol(Cf));
@@ -662,13 +671,13 @@ __global__ __launch_bounds__(kWinLanes) void k_row_segwin(Img g, SegBufs sb) {
             // best of segment c at j..j+3, from LDS when it is loaded
             auto visit = [&](int c) {
                 if (c >= lo && c <= hi) {
-                    const int b0 = (c - lo) * kSegL;
+                    const int b0 = (c - lo) * L;
                     seg_best4(sh.cand, sh.st, b0, b0 + sh.cnt[c - lo], i, j, W, bd, bf);
                 } else {
-                    seg_best4(erow, srow, c * kSegL, c * kSegL + mrow[c], i, j, W, bd, bf);
+                    seg_best4(erow, srow, c * L, c * L + mrow[c], i, j, W, bd, bf);
                 }
             };
-            // a segment spans at least kSegL >= 16 columns: at most one more
+            // a segment spans at least L >= 16 columns: at most one more
             // starts within the 16 pixels
             int s0 = sh.segof[(j - x0) >> 4];
             if (s0 + 1 < nseg && sh.first[s0 + 1] <= j) ++s0;
@@ -748,7 +757,7 @@ __global__ __launch_bounds__(T, T <= 512 ? 6 : 1) void k_row_segfill(Img g, SegB
     __shared__ SegLds<T, L> sh;
     constexpr int CAP = SegLds<T, L>::CAP, NW = T / 64, PER = CAP / T;
     static_assert(SegLds<T, L>::G <= T, "one lane per segment");
-    static_assert(L == kSegL, "segment envelopes are laid out kSegL slots apart");
+    static_assert(L % kSegL == 0, "segment envelopes are laid out L slots apart");
     const Views v = views_of(g);
     const int n = v.meta[0];
     const int W = g.W;
@@ -926,28 +935,38 @@ hipError_t launch_segfill(const Img& g, const SegBufs& sb, hipStream_t stream) {
     return hipGetLastError();
 }
 
+template <int L>
 hipError_t launch_segwin(const Img& g, const SegBufs& sb, hipStream_t stream) {
     static int per_cu = 0;
-    if (per_cu == 0) per_cu = blocks_per_cu(k_row_segwin, kWinLanes);
+    if (per_cu == 0) per_cu = blocks_per_cu(k_row_segwin<L>, kWinLanes);
     const int total = g.H * ((g.W + kWinTile - 1) / kWinTile);
     const int grid = min(total, per_cu * device_cus());
-    EDT_LAUNCH_AS("k_row_segwin", k_row_segwin, dim3(grid), dim3(kWinLanes), 0, stream, g, sb);
+    EDT_LAUNCH_AS("k_row_segwin", k_row_segwin<L>, dim3(grid), dim3(kWinLanes), 0, stream, g, sb);
     return hipGetLastError();
 }
 
-// Dense rows of one image, squared Euclidean: segment scan, the bounded
-// search over segments, then the merge for the rows it left.
-hipError_t launch_rows_segments(const Img& g, hipStream_t stream) {
-    constexpr int L = kSegL;
-    const SegBufs sb = seg_bufs(g);
-    hipError_t e = launch_row_segscan(g, sb, stream);
-    if (e == hipSuccess) e = launch_segwin(g, sb, stream);
+template <int L>
+hipError_t launch_segments_l(const Img& g, const SegBufs& sb, hipStream_t stream) {
+    hipError_t e = launch_row_segscan(g, L, sb, stream);
+    if (e == hipSuccess) e = launch_segwin<L>(g, sb, stream);
     if (e != hipSuccess) return e;
     const int W = g.W;
     if (W <= 2048) return launch_segfill<128, L>(g, sb, stream);
     if (W <= 4096) return launch_segfill<256, L>(g, sb, stream);
     if (W <= 8192) return launch_segfill<512, L>(g, sb, stream);
     return launch_segfill<1024, L>(g, sb, stream);
+}
+
+// Dense rows of one image, squared Euclidean: segment scan, the bounded
+// search over segments, then the merge for the rows it left.  Segments of
+// 2 kSegL candidates halve the segments a pixel visits and the scan's work
+// items; they pay once the image has at least 4096 such items (measured:
+// 16384^2 disks 2.85 -> 2.54 ms for scan and search, 4096^2 slower).
+hipError_t launch_rows_segments(const Img& g, hipStream_t stream) {
+    const SegBufs sb = seg_bufs(g);
+    const int64_t items = (int64_t)items_lanes(g.H) * ((g.W + 2 * kSegL - 1) / (2 * kSegL));
+    return items >= 4096 ? launch_segments_l<2 * kSegL>(g, sb, stream)
+                         : launch_segments_l<kSegL>(g, sb, stream);
 }
 
 template <int kM>

@@ -171,11 +171,22 @@ __device__ __forceinline__ void fill_block(int b, const uint32_t* sc, const int1
 // piece, and a pop below the ring brings a block back, so the loop touches
 // memory in whole 64- and 32-byte pieces and waits for it only when it reads
 // the next 32 site rows or, rarely, brings a block back.
-template <bool kPk>
+// With kPf the site rows of the next 32 candidates are loaded while the
+// current ones are scanned (16 more registers: the segment scan of single
+// images, whose work items are short, takes it; the batch kernel keeps its
+// registers for occupancy).
+template <bool kPk, bool kPf = false>
 __device__ __forceinline__ int scan_row(const int i, const int n, const int W,
                                         const int16_t* __restrict__ cols, int16_t* rr,
                                         uint32_t* sc, const bool vec, LaneRing<kPk>& ring,
                                         const int lane, const bool tl) {
+    int4 pf0, pf1, pf2, pf3;
+    if (kPf) {
+        pf0 = *reinterpret_cast<const int4*>(rr);
+        pf1 = *reinterpret_cast<const int4*>(rr + 8);
+        pf2 = *reinterpret_cast<const int4*>(rr + 16);
+        pf3 = *reinterpret_cast<const int4*>(rr + 24);
+    }
     int M = 0, base = 0;
     int colA = 0, rowA = 0, gA = 0, sA = 0;  // top entry (M - 1)
     int dAs = 0, dAe = 0;  // the top's distances at its start sA and at pixel W - 1
@@ -183,10 +194,27 @@ __device__ __forceinline__ int scan_row(const int i, const int n, const int W,
     int sB = 0;
     for (int q0 = 0; q0 < n; q0 += kBlk) {
         static_assert(kBlk == 32, "four 16-byte loads of site rows per block");
-        const int4 rv0 = *reinterpret_cast<const int4*>(rr + q0);
-        const int4 rv1 = *reinterpret_cast<const int4*>(rr + q0 + 8);
-        const int4 rv2 = *reinterpret_cast<const int4*>(rr + q0 + 16);
-        const int4 rv3 = *reinterpret_cast<const int4*>(rr + q0 + 24);
+        int4 rv0, rv1, rv2, rv3;
+        if (kPf) {
+            rv0 = pf0;
+            rv1 = pf1;
+            rv2 = pf2;
+            rv3 = pf3;
+            // the next block lies inside the row's list whenever it starts
+            // before n (the list's pitch is a multiple of 32), and the scan
+            // writes starts only at ranks below the current candidate
+            if (q0 + kBlk < n) {
+                pf0 = *reinterpret_cast<const int4*>(rr + q0 + kBlk);
+                pf1 = *reinterpret_cast<const int4*>(rr + q0 + kBlk + 8);
+                pf2 = *reinterpret_cast<const int4*>(rr + q0 + kBlk + 16);
+                pf3 = *reinterpret_cast<const int4*>(rr + q0 + kBlk + 24);
+            }
+        } else {
+            rv0 = *reinterpret_cast<const int4*>(rr + q0);
+            rv1 = *reinterpret_cast<const int4*>(rr + q0 + 8);
+            rv2 = *reinterpret_cast<const int4*>(rr + q0 + 16);
+            rv3 = *reinterpret_cast<const int4*>(rr + q0 + 24);
+        }
         const int4 cv0 = *reinterpret_cast<const int4*>(cols + q0);
         const int4 cv1 = *reinterpret_cast<const int4*>(cols + q0 + 8);
         const int4 cv2 = *reinterpret_cast<const int4*>(cols + q0 + 16);
@@ -385,7 +413,7 @@ __global__ __launch_bounds__(kLaneRows) void k_row_lanes_batch(BatchTable tb) {
 template <int L>
 __global__ __launch_bounds__(kLaneRows) void k_row_segscan(Img g, SegBufs b) {
     __shared__ LaneRing<false> ring;
-    static_assert(L == kSegL, "segment envelopes are laid out kSegL slots apart");
+    static_assert(L % kSegL == 0 && L % kBlk == 0, "segments of whole 32-candidate blocks");
     const Views v = views_of(g);
     const int n = v.meta[0];
     if (n <= kSparseMaxN) return;
@@ -399,9 +427,9 @@ __global__ __launch_bounds__(kLaneRows) void k_row_segscan(Img g, SegBufs b) {
         const int i = grp * kLaneRows + lane;
         if (i < g.H) {
             uint32_t* sc = b.env + (int64_t)i * pitch + q0;
-            const int M = scan_row<false>(i, min(L, n - q0), g.W, v.cols + q0,
-                                          v.rc + (int64_t)i * pitch + q0, sc, true, ring, lane,
-                                          false);
+            const int M = scan_row<false, true>(i, min(L, n - q0), g.W, v.cols + q0,
+                                                v.rc + (int64_t)i * pitch + q0, sc, true, ring,
+                                                lane, false);
             b.segm[(int64_t)i * seg_count(g.W) + y] = (int16_t)M;
             if (y == 0) b.rowfail[i] = 0;
         }
@@ -417,16 +445,21 @@ int lane_blocks_per_cu(K kernel) {
     return nb;
 }
 
+template <int L>
+hipError_t launch_segscan_l(const Img& g, const SegBufs& b, hipStream_t stream) {
+    static int per_cu = 0;
+    const int most = items_lanes(g.H) * ((g.W + L - 1) / L);  // items if every column is listed
+    if (per_cu == 0) per_cu = lane_blocks_per_cu(k_row_segscan<L>);
+    const int grid = min(most, per_cu * device_cus());
+    EDT_LAUNCH_AS("k_row_segscan", k_row_segscan<L>, dim3(grid), dim3(kLaneRows), 0, stream, g, b);
+    return hipGetLastError();
+}
+
 }  // namespace
 
-hipError_t launch_row_segscan(const Img& g, const SegBufs& b, hipStream_t stream) {
-    static int per_cu = 0;
-    const int most = items_lanes(g.H) * seg_count(g.W);  // items if every column is listed
-    if (per_cu == 0) per_cu = lane_blocks_per_cu(k_row_segscan<kSegL>);
-    const int grid = min(most, per_cu * device_cus());
-    EDT_LAUNCH_AS("k_row_segscan", k_row_segscan<kSegL>, dim3(grid), dim3(kLaneRows), 0, stream,
-                  g, b);
-    return hipGetLastError();
+hipError_t launch_row_segscan(const Img& g, int L, const SegBufs& b, hipStream_t stream) {
+    return L == 2 * kSegL ? launch_segscan_l<2 * kSegL>(g, b, stream)
+                          : launch_segscan_l<kSegL>(g, b, stream);
 }
 
 hipError_t launch_row_lanes_batch(const BatchTable& tb, int total, hipStream_t stream) {

@@ -95,6 +95,26 @@ def test_disks_4096_every_pixel_against_the_oracle(edt, pol):
     assert np.array_equal(d.ravel()[lin], Db) and np.array_equal(f.ravel()[lin], Fb)
 
 
+@pytest.mark.parametrize("pol", [0, 1])
+def test_dense_16384_every_pixel_against_the_oracle(edt, pol):
+    # the dense 16384^2 disk image (3200 disks of radius 5-200 and isolated
+    # points) in the configuration bench.py times: segments of 128 candidates,
+    # the bounded search over them and the merge for the rows it leaves
+    import torch
+    m = workloads.disks(16384, 16384, n_disks=3200)
+    D, F = _feature_full(edt, m, pol)
+    d, f = D.cpu().numpy(), F.cpu().numpy()
+    del D, F
+    torch.cuda.empty_cache()
+    Do, Fo = oracle.separable(m, pol)
+    assert np.array_equal(d, Do) and np.array_equal(f, Fo)
+    del Do, Fo
+    rng = np.random.default_rng(10 + pol)
+    lin = rng.choice(m.size, 2000, replace=False)
+    Db, Fb = oracle.brute_at(m, lin, pol)
+    assert np.array_equal(d.ravel()[lin], Db) and np.array_equal(f.ravel()[lin], Fb)
+
+
 def test_batch_2048_every_image_against_the_oracle(edt):
     import torch
     dev = torch.device("cuda:0")
