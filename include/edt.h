@@ -415,6 +415,18 @@ edt_status edt_profile_begin(void);
  * timed.  Returns EDT_ERR_DEVICE if an event could not be read. */
 edt_status edt_profile_end(edt_kernel_time *out, int32_t capacity, int32_t *count);
 
+/* ---- testing ---------------------------------------------------------- */
+
+/* Arm a launch failure, for tests of the error paths: the k-th kernel launch
+ * of the library from now on (k >= 1, counted over all threads and entry
+ * points) is not enqueued, nor is any later launch of the same call, and the
+ * call reports the failure as a failed launch would (EDT_ERR_DEVICE; for a
+ * served request, its ticket's status).  The failed call's outputs are
+ * undefined; no kernel runs on state a skipped one should have written.  A
+ * batch submission that replays a captured graph launches no kernel through
+ * this path.  k = 0 disarms.  Errors: EDT_ERR_INVALID_ARG for k < 0. */
+edt_status edt_debug_fail_launch(int32_t k);
+
 #ifdef __cplusplus
 }
 #endif

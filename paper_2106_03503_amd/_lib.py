@@ -57,6 +57,8 @@ def _load():
     lib.edt_regions.restype = i32
     lib.edt_danielsson.argtypes = [P, i32, i32, i64, i32, P, P, i64, P]
     lib.edt_danielsson.restype = i32
+    lib.edt_debug_fail_launch.argtypes = [i32]
+    lib.edt_debug_fail_launch.restype = i32
     lib.edt_profile_begin.argtypes = []
     lib.edt_profile_begin.restype = i32
     lib.edt_profile_end.argtypes = [P, i32, P]

@@ -56,7 +56,7 @@ hipError_t launch_sqrt(const int32_t* D, float* out, int64_t n, hipStream_t stre
     int64_t blocks = (n + 255) / 256;
     if (blocks > 8192) blocks = 8192;
     EDT_LAUNCH(k_sqrt, dim3((unsigned)blocks), dim3(256), 0, stream, D, out, n);
-    return hipGetLastError();
+    return launch_status();
 }
 
 edt_status check_image(const uint8_t* mask, int32_t H, int32_t W, int64_t mask_pitch,

@@ -285,9 +285,10 @@ hipError_t enqueue(edt_plan* p, const Schedule& sc, const uint8_t* mask_base, in
     for (size_t k = 0; k < sc.singles.size() && e == hipSuccess; ++k)
         e = enqueue_single_image(p, sc.singles[k], mask_base, dist_base, feat_base, workspace,
                                  two && (k & 1) ? aux : s);
-    if (two && e == hipSuccess) {
-        e = hipEventRecord(p->join, aux);
-        if (e == hipSuccess) e = hipStreamWaitEvent(s, p->join, 0);
+    if (two) {  // joined back even after a failure, so that no capture is left open on aux
+        const hipError_t j = hipEventRecord(p->join, aux);
+        const hipError_t w = j == hipSuccess ? hipStreamWaitEvent(s, p->join, 0) : j;
+        if (e == hipSuccess) e = w;
     }
     return e;
 }

@@ -429,7 +429,7 @@ hipError_t launch_column_pass(const Img& g, hipStream_t stream) {
     const int near = (items_near(g.H, g.W) + kColWaves - 1) / kColWaves;
     EDT_LAUNCH_AS("k_nearest_row", k_near, dim3(near < 2048 ? near : 2048), dim3(64 * kColWaves),
                   0, stream, g);
-    return hipGetLastError();
+    return launch_status();
 }
 
 hipError_t launch_column_pass_batch(const BatchTable& t, const int* totals, hipStream_t stream) {
@@ -444,7 +444,7 @@ hipError_t launch_column_pass_batch(const BatchTable& t, const int* totals, hipS
                   stream, t, totals[kPhCompact]);
     EDT_LAUNCH_AS("k_nearest_row", k_near_batch, wave_grid(totals[kPhNear]),
                   dim3(64 * kColWaves), 0, stream, t, totals[kPhNear]);
-    return hipGetLastError();
+    return launch_status();
 }
 
 }  // namespace edt

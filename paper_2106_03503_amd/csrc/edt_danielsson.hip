@@ -138,7 +138,7 @@ edt_status edt_danielsson(const uint8_t* mask, int32_t H, int32_t W, int64_t mas
     EDT_LAUNCH_AS("k_danielsson", edt::k_danielsson, dim3(1), dim3(64), 0,
                   reinterpret_cast<hipStream_t>(stream), mask, mask_pitch, H, W, polarity,
                   dist_sq, rel, out_pitch);
-    return hipGetLastError() == hipSuccess ? EDT_OK : EDT_ERR_DEVICE;
+    return edt::launch_status() == hipSuccess ? EDT_OK : EDT_ERR_DEVICE;
 }
 
 }  // extern "C"

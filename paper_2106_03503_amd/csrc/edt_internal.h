@@ -380,10 +380,19 @@ bool prof_enabled();
 int prof_begin(const char* name, hipStream_t stream);
 void prof_end(int token, hipStream_t stream);
 
+// Launch-failure injection for tests of the error paths
+// (edt_debug_fail_launch): skip_launch() is true for the armed launch and, on
+// that thread, for every later launch until launch_status() reports the
+// failure, so that no kernel runs on the state a skipped one should have
+// written.  launch_status() is hipGetLastError(), or the injected failure.
+bool skip_launch();
+hipError_t launch_status();
+
 // Launch a kernel on a stream, bracketed by timing events (recorded under
 // `name`) when enabled.
 #define EDT_LAUNCH_AS(name, kernel, grid, block, lds, stream, ...)           \
     do {                                                                     \
+        if (::edt::skip_launch()) break;                                     \
         const int edt_tok_ = ::edt::prof_begin(name, stream);                \
         hipLaunchKernelGGL(kernel, grid, block, lds, stream, __VA_ARGS__);   \
         ::edt::prof_end(edt_tok_, stream);                                   \

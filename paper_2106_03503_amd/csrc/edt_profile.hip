@@ -4,6 +4,7 @@
 #include "../../include/edt.h"
 #include "edt_internal.h"
 
+#include <atomic>
 #include <mutex>
 #include <string.h>
 #include <vector>
@@ -40,6 +41,30 @@ Profiler& prof() {
 }
 
 }  // namespace
+
+// Launches until the armed failure (0: none armed), and whether this thread
+// has a failure to report.
+std::atomic<int64_t> g_fail_in{0};
+thread_local bool t_failed = false;
+
+bool skip_launch() {
+    if (t_failed) return true;
+    if (g_fail_in.load(std::memory_order_relaxed) <= 0) return false;
+    if (g_fail_in.fetch_sub(1) == 1) {
+        t_failed = true;
+        return true;
+    }
+    return false;
+}
+
+hipError_t launch_status() {
+    const hipError_t e = hipGetLastError();
+    if (t_failed) {
+        t_failed = false;
+        return hipErrorLaunchFailure;
+    }
+    return e;
+}
 
 bool prof_enabled() {
     Profiler& p = prof();
@@ -121,3 +146,9 @@ edt_status edt_profile_end(edt_kernel_time* out, int32_t capacity, int32_t* coun
 }
 
 }  // extern "C"
+
+extern "C" edt_status edt_debug_fail_launch(int32_t k) {
+    if (k < 0) return EDT_ERR_INVALID_ARG;
+    edt::g_fail_in.store(k);
+    return EDT_OK;
+}

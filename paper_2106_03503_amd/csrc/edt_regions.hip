@@ -203,7 +203,7 @@ edt_status edt_regions(const uint8_t* mask, int32_t H, int32_t W, int64_t mask_p
     EDT_LAUNCH_AS("k_reg_flatten", edt::k_reg_flatten, grid, block, 0, s, g);
     EDT_LAUNCH_AS("k_reg_others", edt::k_reg_others, grid, block, 0, s, g);
     EDT_LAUNCH_AS("k_reg_sites", edt::k_reg_sites, grid, block, 0, s, g);
-    return hipGetLastError() == hipSuccess ? EDT_OK : EDT_ERR_DEVICE;
+    return edt::launch_status() == hipSuccess ? EDT_OK : EDT_ERR_DEVICE;
 }
 
 }  // extern "C"

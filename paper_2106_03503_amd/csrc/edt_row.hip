@@ -910,7 +910,7 @@ hipError_t launch_single(const Img& g, uint8_t* slots, hipStream_t stream) {
     const char* name = kSparse ? "k_row_sparse" : (kGlobal ? "k_row_dense_global" : "k_row_dense");
     EDT_LAUNCH_AS(name, (k_row_single<kM, T, S, kSparse, kGlobal>), dim3(grid), dim3(T), 0, stream,
                   g, slots);
-    return hipGetLastError();
+    return launch_status();
 }
 
 template <int T, int S, bool kSparse>
@@ -922,7 +922,7 @@ hipError_t launch_batch(const BatchTable& tb, int total, hipStream_t stream) {
     if (grid < 1) return hipSuccess;
     const char* name = kSparse ? "k_row_sparse" : "k_row_dense";
     EDT_LAUNCH_AS(name, (k_row_batch<T, S, kSparse>), dim3(grid), dim3(T), 0, stream, tb, total);
-    return hipGetLastError();
+    return launch_status();
 }
 
 template <int T, int L>
@@ -932,7 +932,7 @@ hipError_t launch_segfill(const Img& g, const SegBufs& sb, hipStream_t stream) {
     int grid = per_cu * device_cus();
     if (grid > g.H) grid = g.H;
     EDT_LAUNCH_AS("k_row_segfill", (k_row_segfill<T, L>), dim3(grid), dim3(T), 0, stream, g, sb);
-    return hipGetLastError();
+    return launch_status();
 }
 
 template <int L>
@@ -942,7 +942,7 @@ hipError_t launch_segwin(const Img& g, const SegBufs& sb, hipStream_t stream) {
     const int total = g.H * ((g.W + kWinTile - 1) / kWinTile);
     const int grid = min(total, per_cu * device_cus());
     EDT_LAUNCH_AS("k_row_segwin", k_row_segwin<L>, dim3(grid), dim3(kWinLanes), 0, stream, g, sb);
-    return hipGetLastError();
+    return launch_status();
 }
 
 template <int L>

@@ -452,7 +452,7 @@ hipError_t launch_segscan_l(const Img& g, const SegBufs& b, hipStream_t stream) 
     if (per_cu == 0) per_cu = lane_blocks_per_cu(k_row_segscan<L>);
     const int grid = min(most, per_cu * device_cus());
     EDT_LAUNCH_AS("k_row_segscan", k_row_segscan<L>, dim3(grid), dim3(kLaneRows), 0, stream, g, b);
-    return hipGetLastError();
+    return launch_status();
 }
 
 }  // namespace
@@ -465,7 +465,7 @@ hipError_t launch_row_segscan(const Img& g, int L, const SegBufs& b, hipStream_t
 hipError_t launch_row_lanes_batch(const BatchTable& tb, int total, hipStream_t stream) {
     if (total < 1) return hipSuccess;
     EDT_LAUNCH_AS("k_row_lanes", k_row_lanes_batch, dim3(total), dim3(kLaneRows), 0, stream, tb);
-    return hipGetLastError();
+    return launch_status();
 }
 
 }  // namespace edt

@@ -403,21 +403,29 @@ edt_status edt_serve_wait(edt_server* s, uint64_t ticket, int64_t timeout_ns) {
 
 edt_status edt_serve_stats(edt_server* s, edt_serve_counters* out) {
     if (!s || !out) return EDT_ERR_INVALID_ARG;
-    std::lock_guard<std::mutex> lk(s->mu);
-    *out = s->st;
-    out->p50_ns = edt::percentile(s->lat_ns, 0.50);
-    out->p99_ns = edt::percentile(s->lat_ns, 0.99);
+    // copy under the lock, sort outside it: the scheduler retires requests
+    // and admits new ones under the same lock
+    std::vector<double> lat;
+    edt_serve_counters c;
+    double span = 0.0;
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        c = s->st;
+        lat = s->lat_ns;
+        if (s->any && s->st.done > 0)
+            span = std::chrono::duration<double>(s->t_last - s->t_first).count();
+    }
+    c.p50_ns = edt::percentile(lat, 0.50);
+    c.p99_ns = edt::percentile(lat, 0.99);
     double sum = 0.0, mx = 0.0;
-    for (double v : s->lat_ns) {
+    for (double v : lat) {
         sum += v;
         if (v > mx) mx = v;
     }
-    out->mean_ns = s->lat_ns.empty() ? 0.0 : sum / (double)s->lat_ns.size();
-    out->max_ns = mx;
-    const double span =
-        s->any && s->st.done > 0 ? std::chrono::duration<double>(s->t_last - s->t_first).count()
-                                 : 0.0;
-    out->gpix_per_s = span > 0.0 ? (double)s->st.pixels_done / span / 1e9 : 0.0;
+    c.mean_ns = lat.empty() ? 0.0 : sum / (double)lat.size();
+    c.max_ns = mx;
+    c.gpix_per_s = span > 0.0 ? (double)c.pixels_done / span / 1e9 : 0.0;
+    *out = c;
     return EDT_OK;
 }
 

@@ -162,7 +162,7 @@ hipError_t launch_transpose_in(const BatchTable& t, int total, hipStream_t strea
     if (per_cu == 0) per_cu = blocks_per_cu(k_tr_in);
     const int grid = min(total, per_cu * device_cus());
     EDT_LAUNCH(k_tr_in, dim3(grid), dim3(kTrThreads), 0, stream, t, total);
-    return hipGetLastError();
+    return launch_status();
 }
 
 hipError_t launch_transpose_out(const BatchTable& t, int total, hipStream_t stream) {
@@ -171,7 +171,7 @@ hipError_t launch_transpose_out(const BatchTable& t, int total, hipStream_t stre
     if (per_cu == 0) per_cu = blocks_per_cu(k_tr_out);
     const int grid = min(total, per_cu * device_cus());
     EDT_LAUNCH(k_tr_out, dim3(grid), dim3(kTrThreads), 0, stream, t, total);
-    return hipGetLastError();
+    return launch_status();
 }
 
 }  // namespace edt
