@@ -249,3 +249,23 @@ def test_dense_rows_with_far_sites(edt, kind):
         m[1:, :] = (np.random.default_rng(5).random((H - 1, W)) < 2e-5)
     check_exact(edt, m, 0)
     check_exact(edt, m, 1)
+
+
+@pytest.mark.parametrize("W", [2100, 4097, 9000])
+def test_segment_path_with_ties(edt, W):
+    # more than 1024 listed columns (the segment scan and the bounded search
+    # over segments) on tie-heavy masks: a regular grid of sites, where many
+    # pixels are equidistant from several sites, and a mirror-symmetric mask
+    H = 150
+    g = np.zeros((H, W), np.uint8)
+    g[::5, ::2] = 1
+    check_exact(edt, g, 0)
+    check_exact(edt, g, 1)
+    rng = np.random.default_rng(W)
+    half = (rng.random((H, W // 2)) < 0.01).astype(np.uint8)
+    half[:, ::3] |= (rng.random((H, (W // 2 + 2) // 3)) < 0.05).astype(np.uint8)
+    m = np.concatenate([half, half[:, ::-1]], axis=1)
+    m = np.concatenate([m, np.zeros((H, W - m.shape[1]), np.uint8)], axis=1)
+    m[: H // 2] |= m[H // 2:][: H // 2][::-1]
+    check_exact(edt, m, 0)
+    check_exact(edt, m, 1)
