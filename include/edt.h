@@ -310,7 +310,11 @@ edt_status edt_plan_destroy(edt_plan *plan);
  * launches of edt_batch_submit) or, for a lone request, as a single
  * transform; a request wider than 1024 columns is always launched alone (it
  * fills the GPU by itself).  Requests arriving meanwhile join the next
- * launch.  Workspaces are carved from a caller-owned device arena.
+ * launch.  Workspaces are carved from a caller-owned device arena: a
+ * request takes edt_workspace_bytes(H, W, 1) bytes, and, when max_group > 1
+ * and the image is at most 1024 wide and 4096 tall, 4 more bytes per pixel
+ * of its rows rounded up to 32 columns (the envelopes of the batch row pass),
+ * each rounded up to 256 bytes.
  * Results are bit-identical to edt_feature / edt_sq on the request alone. */
 typedef struct {
     size_t hbm_budget_bytes; /* arena bytes the server may hold at once for

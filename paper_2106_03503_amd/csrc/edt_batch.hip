@@ -337,8 +337,7 @@ edt_status edt_batch_plan(const edt_image_desc* images, int32_t n, int32_t want_
         if (st != EDT_OK) return st;
         if (d.W > EDT_BATCH_MAX_W) return EDT_ERR_TOO_LARGE;
         if (d.mask_offset < 0 || d.out_offset < 0) return EDT_ERR_INVALID_ARG;
-        // every image writes something: the one-lane-per-row pass keeps a
-        // row's stack in that row's output until the row is filled
+        // every image asks for at least one output
         if (!want_dist && !d.want_feature) return EDT_ERR_INVALID_ARG;
         edt::BatchImage& b = img[q];
         b.mask_off = d.mask_offset;
@@ -356,7 +355,8 @@ edt_status edt_batch_plan(const edt_image_desc* images, int32_t n, int32_t want_
         // workspace adds the segment buffers and row slots; images wider than
         // tall may run as their transposes, with transposed copies of the mask
         // and outputs
-        size_t need = edt::layout_for(d.H, d.W, d.W > edt::kLaneMaxW).total;
+        size_t need =
+            edt::layout_for(d.H, d.W, d.W > edt::kLaneMaxW, edt::lane_image(d.H, d.W)).total;
         if (d.W > d.H && d.H <= edt::kLaneMaxW && d.W <= edt::kLanePackMaxH)
             need = std::max(need, edt::tr_layout(d.W, d.H).total);
         b.tr = 0;

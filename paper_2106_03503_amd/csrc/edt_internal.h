@@ -57,6 +57,8 @@ struct Layout {
     size_t env;        // uint32 [H][cand_pitch(W)] segment envelopes (packed candidates)
     size_t rowfail;    // uint8  [H]      row left to the segment merge
     size_t slots;      // row slots for rows wider than kLdsMaxW (single images only)
+    size_t stk;        // uint32 [H][cand_pitch(W)] envelopes of the one-lane-per-row pass
+                       // (batch images it takes only), laid out per 64-row work item
     size_t total;
 };
 
@@ -68,8 +70,11 @@ __host__ __device__ inline int seg_count(int W) { return (W + kSegL - 1) / kSegL
 __host__ __device__ inline bool has_segments(int W) { return W > kSparseMaxN && W <= kLdsMaxW; }
 
 // Workspace layout of one image; with_slots adds the global row slots and
-// segment sizes that the single-image row pass uses for wide rows.
-__host__ __device__ inline Layout layout_for(int H, int W, bool with_slots = true) {
+// segment sizes that the single-image row pass uses for wide rows, with_stack
+// the envelopes of the one-lane-per-row pass (last, so that no other offset
+// depends on it).
+__host__ __device__ inline Layout layout_for(int H, int W, bool with_slots = true,
+                                             bool with_stack = false) {
     Layout L;
     L.nb = (H + kBand - 1) / kBand;
     const size_t cp = (size_t)cand_pitch(W);
@@ -96,6 +101,8 @@ __host__ __device__ inline Layout layout_for(int H, int W, bool with_slots = tru
     if (with_slots && has_segments(W)) off = align_up(off + (size_t)H, 256);
     L.slots = off;
     if (with_slots && W > kLdsMaxW) off = align_up(off + (size_t)kWideSlots * wide_slot_bytes(), 256);
+    L.stk = off;
+    if (with_stack) off = align_up(off + (size_t)H * cp * 4, 256);
     L.total = off;
     return L;
 }
@@ -167,6 +174,11 @@ constexpr int kLaneMaxW = 1024;
 // site row into 12 bits).
 constexpr int kLanePackMaxH = 4096;
 __host__ __device__ inline int items_lanes(int H) { return (H + kLaneRows - 1) / kLaneRows; }
+// An image the one-lane-per-row pass can take (its workspace then holds the
+// envelopes of that pass).
+__host__ __device__ inline bool lane_image(int H, int W) {
+    return W <= kLaneMaxW && H <= kLanePackMaxH;
+}
 
 // Phases of the transform, in launch order (a batch image's rows are work
 // items of kPhRows, or row groups of kPhLanes when its width is at most the
@@ -287,7 +299,7 @@ __host__ __device__ inline TrLayout tr_layout(int H, int W) {
     TrLayout T;
     T.mpitch = (int64_t)align_up((size_t)W, 16);
     T.opitch = (int64_t)align_up((size_t)W, 4);
-    size_t off = align_up(layout_for(H, W, false).total, 256);
+    size_t off = align_up(layout_for(H, W, false, true).total, 256);
     T.mask = off;
     off = align_up(off + (size_t)H * T.mpitch, 256);
     T.dist = off;

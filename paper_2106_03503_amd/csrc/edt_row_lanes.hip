@@ -14,12 +14,17 @@
 // eq_intersection.
 //
 // Where the stack lives: the top entries in registers and an LDS ring; older
-// entries in memory, entry e (packed column and site row) at slot e of the
-// row's own output and its start at slot e of the row's list of site rows,
-// which the scan has already read there (e never exceeds the index of the
-// candidate being scanned).  Once every lane has finished, the wavefront
-// fills the rows one by one: a row's whole envelope is copied into LDS before
-// any of its pixels is written.
+// entries in memory, in blocks of RB entries.  In the batch kernel a work
+// item's blocks sit in the image's workspace block-major: block k of the
+// item's row r at 32-byte piece k * rows + r, so that a block is one whole
+// 32-byte piece of memory and the lanes that move their k-th block together
+// write one contiguous run (a piece per lane in each row's own output would
+// be written as partial pieces wherever a row does not start on 32 bytes).
+// Once every lane has finished, the wavefront fills the rows one by one from
+// each row's envelope copied into LDS.  The segment scan of single images
+// keeps the unpacked layout: entry e at slot e of its own row of envelopes
+// and its start at slot e of the row's list of site rows, which the scan has
+// already read there (e never exceeds the index of the candidate scanned).
 #include "edt_internal.h"
 
 namespace edt {
@@ -95,8 +100,8 @@ __device__ __forceinline__ int last_at_or_before(const uint32_t* c, int lo, int 
     return a;
 }
 
-// Move ring block [b, b + RB) of this lane to memory (ranks b.. of sc, and of
-// rr for the unpacked starts); b is a multiple of RB.
+// Move ring block [b, b + RB) of this lane to memory (the RB words at sc, and
+// ranks b.. of rr for the unpacked starts); b is a multiple of RB.
 template <bool kPk>
 __device__ __forceinline__ void spill_block(int b, uint32_t* sc, int16_t* rr, bool vec,
                                             LaneRing<kPk>& ring, int lane) {
@@ -108,11 +113,11 @@ __device__ __forceinline__ void spill_block(int b, uint32_t* sc, int16_t* rr, bo
 #pragma unroll
         for (int k = 0; k < RB / 4; ++k) {
             const v4i x = {(int)c[4 * k], (int)c[4 * k + 1], (int)c[4 * k + 2], (int)c[4 * k + 3]};
-            *reinterpret_cast<v4i*>(sc + b + 4 * k) = x;
+            *reinterpret_cast<v4i*>(sc + 4 * k) = x;
         }
     } else {
 #pragma unroll
-        for (int k = 0; k < RB; ++k) sc[b + k] = c[k];
+        for (int k = 0; k < RB; ++k) sc[k] = c[k];
     }
     if constexpr (!kPk) {
         uint32_t sp[RB / 2];
@@ -127,7 +132,8 @@ __device__ __forceinline__ void spill_block(int b, uint32_t* sc, int16_t* rr, bo
     }
 }
 
-// Bring block [b, b + RB) of this lane back from memory into the ring.
+// Bring block [b, b + RB) of this lane back from memory (the RB words at sc)
+// into the ring.
 template <bool kPk>
 __device__ __forceinline__ void fill_block(int b, const uint32_t* sc, const int16_t* rr, bool vec,
                                            LaneRing<kPk>& ring, int lane) {
@@ -136,7 +142,7 @@ __device__ __forceinline__ void fill_block(int b, const uint32_t* sc, const int1
     if (vec) {
 #pragma unroll
         for (int k = 0; k < RB / 4; ++k) {
-            const int4 x = *reinterpret_cast<const int4*>(sc + b + 4 * k);
+            const int4 x = *reinterpret_cast<const int4*>(sc + 4 * k);
             c[4 * k] = (uint32_t)x.x;
             c[4 * k + 1] = (uint32_t)x.y;
             c[4 * k + 2] = (uint32_t)x.z;
@@ -144,7 +150,7 @@ __device__ __forceinline__ void fill_block(int b, const uint32_t* sc, const int1
         }
     } else {
 #pragma unroll
-        for (int k = 0; k < RB; ++k) c[k] = sc[b + k];
+        for (int k = 0; k < RB; ++k) c[k] = sc[k];
     }
 #pragma unroll
     for (int k = 0; k < RB; ++k) ring.c[s0 + k][lane] = c[k];
@@ -165,7 +171,8 @@ __device__ __forceinline__ void fill_block(int b, const uint32_t* sc, const int1
 }
 
 // Scan of row i (this lane's row): builds the row's envelope as a stack and
-// leaves it in memory, entry e at rank e of (sc, rr); returns its size.  The
+// leaves it in memory, block e / RB at sc + (e / RB) ld (and the unpacked
+// starts at rank e of rr); returns its size.  The
 // top two entries stay in registers and the ranks [base, M) in an LDS ring of
 // two blocks of R/2 entries; a full ring moves its older block to memory in one
 // piece, and a pop below the ring brings a block back, so the loop touches
@@ -178,8 +185,8 @@ __device__ __forceinline__ void fill_block(int b, const uint32_t* sc, const int1
 template <bool kPk, bool kPf = false>
 __device__ __forceinline__ int scan_row(const int i, const int n, const int W,
                                         const int16_t* __restrict__ cols, int16_t* rr,
-                                        uint32_t* sc, const bool vec, LaneRing<kPk>& ring,
-                                        const int lane, const bool tl) {
+                                        uint32_t* sc, const int ld, const bool vec,
+                                        LaneRing<kPk>& ring, const int lane, const bool tl) {
     int4 pf0, pf1, pf2, pf3;
     if (kPf) {
         pf0 = *reinterpret_cast<const int4*>(rr);
@@ -257,7 +264,7 @@ __device__ __forceinline__ int scan_row(const int i, const int n, const int W,
                         const int e = M - 2;
                         if (e < base) {  // below the ring: bring its block back
                             base -= RB;
-                            fill_block<kPk>(base, sc, rr, vec, ring, lane);
+                            fill_block<kPk>(base, sc + (base / RB) * ld, rr, vec, ring, lane);
                         }
                         cB = ring.c[e & (R - 1)][lane];
                         if constexpr (!kPk) sB = ring.s[e & (R - 1)][lane];
@@ -278,7 +285,7 @@ __device__ __forceinline__ int scan_row(const int i, const int n, const int W,
                     }
                 }
                 if (M - base == R) {  // ring full: its older block goes to memory
-                    spill_block<kPk>(base, sc, rr, vec, ring, lane);
+                    spill_block<kPk>(base, sc + (base / RB) * ld, rr, vec, ring, lane);
                     base += RB;
                 }
                 if constexpr (kPk) {
@@ -297,9 +304,15 @@ __device__ __forceinline__ int scan_row(const int i, const int n, const int W,
             }
         }
     }
-    for (int e = base; e < M; ++e) {  // the rest of the stack to memory
-        sc[e] = ring.c[e & (R - 1)][lane];
-        if constexpr (!kPk) rr[e] = ring.s[e & (R - 1)][lane];
+    // the rest of the stack to memory: whole blocks when packed (slots past
+    // M hold stale entries that nothing reads), entry by entry when not
+    if constexpr (kPk) {
+        for (int b = base; b < M; b += RB) spill_block<kPk>(b, sc + (b / RB) * ld, rr, vec, ring, lane);
+    } else {
+        for (int e = base; e < M; ++e) {
+            sc[e] = ring.c[e & (R - 1)][lane];
+            rr[e] = ring.s[e & (R - 1)][lane];
+        }
     }
     return M;
 }
@@ -320,15 +333,16 @@ __global__ __launch_bounds__(kLaneRows) void k_row_lanes_batch(BatchTable tb) {
     const int n = v.meta[0];
     const int pitch = v.meta[1];
     const int W = g.W;
-    int32_t* base = g.dist ? g.dist : g.feat;  // holds the stacks until the fill
+    // this item's envelopes: block k of row i0 + r at word (k rows + r) RB
+    uint32_t* stk = reinterpret_cast<uint32_t*>(g.ws + layout_for(g.H, g.W, false).stk) +
+                    (int64_t)i0 * cand_pitch(W);
     const bool vec = (!g.dist || reinterpret_cast<uintptr_t>(g.dist) % 16 == 0) &&
                      (!g.feat || reinterpret_cast<uintptr_t>(g.feat) % 16 == 0) &&
                      (g.opitch % 4 == 0);
     if (n > 0 && lane < rows) {
         const int i = i0 + lane;
-        s_m[lane] = scan_row<true>(i, n, W, v.cols, v.rc + (int64_t)i * pitch,
-                                   reinterpret_cast<uint32_t*>(base + (int64_t)i * g.opitch), vec,
-                                   sh.ring, lane, g.tr != 0);
+        s_m[lane] = scan_row<true>(i, n, W, v.cols, v.rc + (int64_t)i * pitch, stk + lane * RB,
+                                   rows * RB, true, sh.ring, lane, g.tr != 0);
     }
     __syncthreads();  // stacks in memory are complete; the ring is free
 
@@ -337,11 +351,13 @@ __global__ __launch_bounds__(kLaneRows) void k_row_lanes_batch(BatchTable tb) {
     uint32_t pc[kPer];
     auto fetch = [&](int r) {
         const int Mr = n > 0 ? s_m[r] : 0;
-        const uint32_t* sc = reinterpret_cast<const uint32_t*>(base + (int64_t)(i0 + r) * g.opitch);
+        // entry e = lane + 64 k: block e / RB = lane / RB + 8 k
+        const uint32_t* sc = stk + (r + (lane / RB) * rows) * RB + (lane & (RB - 1));
+        const int step = (kLaneRows / RB) * rows * RB;
 #pragma unroll
         for (int k = 0; k < kPer; ++k) {
             const int e = lane + k * kLaneRows;
-            if (e < Mr) pc[k] = sc[e];
+            if (e < Mr) pc[k] = sc[k * step];
         }
     };
     if (rows > 0) fetch(0);
@@ -428,8 +444,8 @@ __global__ __launch_bounds__(kLaneRows) void k_row_segscan(Img g, SegBufs b) {
         if (i < g.H) {
             uint32_t* sc = b.env + (int64_t)i * pitch + q0;
             const int M = scan_row<false, true>(i, min(L, n - q0), g.W, v.cols + q0,
-                                                v.rc + (int64_t)i * pitch + q0, sc, true, ring,
-                                                lane, false);
+                                                v.rc + (int64_t)i * pitch + q0, sc, RB, true,
+                                                ring, lane, false);
             b.segm[(int64_t)i * seg_count(g.W) + y] = (int16_t)M;
             if (y == 0) b.rowfail[i] = 0;
         }

@@ -335,7 +335,10 @@ edt_status edt_serve_submit(edt_server* s, const edt_request* r, uint64_t* ticke
     if (c == EDT_OK && ((reinterpret_cast<uintptr_t>(r->dist_sq) & 3) != 0 ||
                         (reinterpret_cast<uintptr_t>(r->feature) & 3) != 0))
         c = EDT_ERR_INVALID_ARG;
-    const size_t bytes = c == EDT_OK ? edt::layout_for(r->H, r->W).total : 0;
+    // a request that may share a launch may take the one-lane-per-row pass,
+    // whose envelopes its workspace then holds as well
+    const bool stack = s->cfg.max_group > 1 && edt::lane_image(r->H, r->W);
+    const size_t bytes = c == EDT_OK ? edt::layout_for(r->H, r->W, true, stack).total : 0;
     if (c == EDT_OK && edt::Arena::round(bytes) > s->alloc.size()) c = EDT_ERR_TOO_LARGE;
     hipEvent_t ev = nullptr;
     {
