@@ -304,16 +304,10 @@ __device__ __forceinline__ int scan_row(const int i, const int n, const int W,
             }
         }
     }
-    // the rest of the stack to memory: whole blocks when packed (slots past
-    // M hold stale entries that nothing reads), entry by entry when not
-    if constexpr (kPk) {
-        for (int b = base; b < M; b += RB) spill_block<kPk>(b, sc + (b / RB) * ld, rr, vec, ring, lane);
-    } else {
-        for (int e = base; e < M; ++e) {
-            sc[e] = ring.c[e & (R - 1)][lane];
-            rr[e] = ring.s[e & (R - 1)][lane];
-        }
-    }
+    // the rest of the stack to memory as whole blocks: the slots past M (up
+    // to the next multiple of RB, within the row's list when n is) take
+    // stale ring entries that nothing reads
+    for (int b = base; b < M; b += RB) spill_block<kPk>(b, sc + (b / RB) * ld, rr, vec, ring, lane);
     return M;
 }
 
