@@ -238,3 +238,20 @@ def test_transposed_order_matches_oracle(edt, lane_w, branches):
 def test_transposed_order_features_only(edt):
     imgs = [(m, pol, True) for m, pol, _ in _wide_images(2106402)[:18]]
     _check_batch(edt, imgs, want_dist=False, submits=1, schedule=(1024, False, 1, False, True))
+
+
+def test_plan_reserves_the_lane_envelopes(edt):
+    """The one-lane-per-row pass keeps each row's envelope in the image's
+    workspace (4 bytes per row per 32-rounded column): a plan reserves that
+    beside the single-image workspace for every image the pass can take, and
+    for the transposed sides of an image that may run as its transpose."""
+    def cp(w):
+        return (w + 31) // 32 * 32
+
+    for H, W in [(1, 1), (33, 70), (300, 1000), (4096, 1024), (700, 64)]:
+        ws = edt.BatchPlan([(H, W, 0, True)]).workspace_bytes
+        assert ws >= edt.workspace_bytes(H, W) + 4 * H * cp(W), (H, W)
+    # wider than tall, at most 1024 tall and 4096 wide: may run transposed
+    H, W = 200, 3000
+    ws = edt.BatchPlan([(H, W, 1, True)]).workspace_bytes
+    assert ws >= edt.workspace_bytes(W, H) + 4 * W * cp(H)
