@@ -447,8 +447,8 @@ __host__ __device__ inline SegBufs seg_bufs(const Img& g) {
     return b;
 }
 // Dense rows of one image (has_segments(W), more than kSparseMaxN candidates,
-// known only on the device): envelopes of row segments of L candidates (kSegL
-// or 2 kSegL), one lane per (row, segment), to `b`, segment c's entries at
+// known only on the device): envelopes of row segments of L candidates (1, 2,
+// 4 or 8 times kSegL), one lane per (row, segment), to `b`, segment c's entries at
 // slots c L + e; every row is marked as not left to the merge.
 hipError_t launch_row_segscan(const Img& g, int L, const SegBufs& b, hipStream_t stream);
 hipError_t launch_sqrt(const int32_t* D, float* out, int64_t n, hipStream_t stream);

@@ -506,22 +506,27 @@ __global__ __launch_bounds__(T) void k_row_single(Img g, uint8_t* __restrict__ s
 // that an equally near site with a smaller index is still seen); every
 // candidate beyond it is farther still.  A work item is one tile of kWinTile
 // pixels of a row; it copies into LDS the segments under the tile and
-// kWinHalo more on each side, and reads a segment beyond those from memory
-// (4096-pixel tiles with two more segments a side were the fastest of the
-// tile widths 1024..8192, halos 1..4 and 256..1024 lanes measured).
+// win_halo<L>() more on each side, and reads a segment beyond those from
+// memory (4096-pixel tiles with two more segments a side were the fastest of
+// the tile widths 1024..8192, halos 1..4 and 256..1024 lanes measured with
+// 64- and 128-candidate segments; 512-candidate segments span at least 512
+// columns, and one more a side is faster there).
 // A row where some pixel would need more than kWinCap segments besides its
 // own is marked in rowfail and done by k_row_segfill instead: its segments
 // are merged up a binary tree (log2(n / L) levels), the survivors compacted,
 // and the row filled from them.
 constexpr int kWinTile = 4096;
 constexpr int kWinLanes = 256;
-constexpr int kWinHalo = 2;
+template <int L>
+constexpr int win_halo() {
+    return L >= 512 ? 1 : 2;
+}
 constexpr int kWinCap = 24;
 // Segments of L candidates: those a tile's columns can touch (each spans at
 // least L columns), plus the halo, and the most a row can have.
 template <int L>
 struct WinShape {
-    static constexpr int kSegs = kWinTile / L + 1 + 2 * kWinHalo;
+    static constexpr int kSegs = kWinTile / L + 1 + 2 * win_halo<L>();
     static constexpr int kMax = kLdsMaxW / L;
     static constexpr int kPer = (kSegs * L + kWinLanes - 1) / kWinLanes;  // slots per lane
 };
@@ -613,8 +618,8 @@ __global__ __launch_bounds__(kWinLanes) void k_row_segwin(Img g, SegBufs sb) {
         const int x0 = (item - i * ntiles) * kWinTile, x1 = min(W, x0 + kWinTile);
         __syncthreads();  // the previous item is done with the LDS copy
         if (t == 0) {
-            s_lo = max(0, seg_at(sh.first, nseg, x0) - kWinHalo);
-            s_hi = min(nseg - 1, seg_at(sh.first, nseg, x1 - 1) + kWinHalo);
+            s_lo = max(0, seg_at(sh.first, nseg, x0) - win_halo<L>());
+            s_hi = min(nseg - 1, seg_at(sh.first, nseg, x1 - 1) + win_halo<L>());
         }
         __syncthreads();
         const int lo = s_lo, hi = s_hi;  // loaded segments [lo, hi], at most WinShape<L>::kSegs
@@ -958,15 +963,20 @@ hipError_t launch_segments_l(const Img& g, const SegBufs& sb, hipStream_t stream
 }
 
 // Dense rows of one image, squared Euclidean: segment scan, the bounded
-// search over segments, then the merge for the rows it left.  Segments of
-// 2 kSegL candidates halve the segments a pixel visits and the scan's work
-// items; they pay once the image has at least 4096 such items (measured:
-// 16384^2 disks 2.85 -> 2.54 ms for scan and search, 4096^2 slower).
+// search over segments, then the merge for the rows it left.  Longer
+// segments cut the segments a pixel visits and the scan's work items; the
+// longest of 512, 256 and 128 candidates that still gives the scan at least
+// 4096 work items is taken, else 64 (measured on 16384^2 disks, scan and
+// search: 2.47 ms with 128, 2.33 with 256, 2.19 with 512 and 2.71 with 1024,
+// 128 having beaten 64 there by 0.3 ms; on 4096^2 disks the longer ones are
+// slower: too few scan items).
 hipError_t launch_rows_segments(const Img& g, hipStream_t stream) {
     const SegBufs sb = seg_bufs(g);
-    const int64_t items = (int64_t)items_lanes(g.H) * ((g.W + 2 * kSegL - 1) / (2 * kSegL));
-    return items >= 4096 ? launch_segments_l<2 * kSegL>(g, sb, stream)
-                         : launch_segments_l<kSegL>(g, sb, stream);
+    auto items = [&](int L) { return (int64_t)items_lanes(g.H) * ((g.W + L - 1) / L); };
+    if (items(8 * kSegL) >= 4096) return launch_segments_l<8 * kSegL>(g, sb, stream);
+    if (items(4 * kSegL) >= 4096) return launch_segments_l<4 * kSegL>(g, sb, stream);
+    if (items(2 * kSegL) >= 4096) return launch_segments_l<2 * kSegL>(g, sb, stream);
+    return launch_segments_l<kSegL>(g, sb, stream);
 }
 
 template <int kM>

@@ -468,8 +468,10 @@ hipError_t launch_segscan_l(const Img& g, const SegBufs& b, hipStream_t stream) 
 }  // namespace
 
 hipError_t launch_row_segscan(const Img& g, int L, const SegBufs& b, hipStream_t stream) {
-    return L == 2 * kSegL ? launch_segscan_l<2 * kSegL>(g, b, stream)
-                          : launch_segscan_l<kSegL>(g, b, stream);
+    if (L == 8 * kSegL) return launch_segscan_l<8 * kSegL>(g, b, stream);
+    if (L == 4 * kSegL) return launch_segscan_l<4 * kSegL>(g, b, stream);
+    if (L == 2 * kSegL) return launch_segscan_l<2 * kSegL>(g, b, stream);
+    return launch_segscan_l<kSegL>(g, b, stream);
 }
 
 hipError_t launch_row_lanes_batch(const BatchTable& tb, int total, hipStream_t stream) {

@@ -7,6 +7,8 @@ configuration bench.py times:
   D = i^2 + j^2, F = 0) and with none (sentinels);
 * 4096 x 4096 disks, both polarities: every pixel against the oracle's
   separable transform, and a sample against its brute force;
+* dense disks at 16384 x 16384 and 8192 x 8192 (segments of 512 and 256
+  candidates), both polarities: the same;
 * the 2048-image ragged batch through edt_batch_submit with the schedule the
   autotuner picks (lanes up to 1024 columns, largest first): every image
   against the oracle's separable transform."""
@@ -98,7 +100,7 @@ def test_disks_4096_every_pixel_against_the_oracle(edt, pol):
 @pytest.mark.parametrize("pol", [0, 1])
 def test_dense_16384_every_pixel_against_the_oracle(edt, pol):
     # the dense 16384^2 disk image (3200 disks of radius 5-200 and isolated
-    # points) in the configuration bench.py times: segments of 128 candidates,
+    # points) in the configuration bench.py times: segments of 512 candidates,
     # the bounded search over them and the merge for the rows it leaves
     import torch
     m = workloads.disks(16384, 16384, n_disks=3200)
@@ -110,6 +112,24 @@ def test_dense_16384_every_pixel_against_the_oracle(edt, pol):
     assert np.array_equal(d, Do) and np.array_equal(f, Fo)
     del Do, Fo
     rng = np.random.default_rng(10 + pol)
+    lin = rng.choice(m.size, 2000, replace=False)
+    Db, Fb = oracle.brute_at(m, lin, pol)
+    assert np.array_equal(d.ravel()[lin], Db) and np.array_equal(f.ravel()[lin], Fb)
+
+
+@pytest.mark.parametrize("pol", [0, 1])
+def test_dense_8192_every_pixel_against_the_oracle(edt, pol):
+    # 8192^2 disks at the density of the 16384^2 image: segments of 256
+    # candidates (the longest length that still gives 4096 scan items here)
+    import torch
+    m = workloads.disks(8192, 8192, n_disks=800)
+    D, F = _feature_full(edt, m, pol)
+    d, f = D.cpu().numpy(), F.cpu().numpy()
+    del D, F
+    torch.cuda.empty_cache()
+    Do, Fo = oracle.separable(m, pol)
+    assert np.array_equal(d, Do) and np.array_equal(f, Fo)
+    rng = np.random.default_rng(20 + pol)
     lin = rng.choice(m.size, 2000, replace=False)
     Db, Fb = oracle.brute_at(m, lin, pol)
     assert np.array_equal(d.ravel()[lin], Db) and np.array_equal(f.ravel()[lin], Fb)
