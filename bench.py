@@ -55,13 +55,16 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published peak
 SWEEP_RATES = (100.0, 250.0, 500.0, 1000.0, 2000.0, 5000.0)
 
 
-def path_bytes(H: int, W: int, n: int, with_feature: bool = True) -> int:
+def path_bytes(H: int, W: int, n: int, with_feature: bool = True, lanes: bool = False) -> int:
     """Bytes the method itself must move for one image: the mask read once, the
     outputs written once (4 B of distance, plus 4 B of feature), and the
     intermediate as this design holds it -- the nearest site row (int16) of
     each of the n columns holding a site, written by the vertical pass and
-    read by the row pass."""
-    return H * W * (1 + 4 + (4 if with_feature else 0)) + 2 * 2 * H * n
+    read by the row pass; for a batch image of the one-lane-per-row pass,
+    which works the rows out itself, the band bits and carries (12 B per
+    column per 64-row band) written and read once instead."""
+    inter = 2 * 12 * ((H + 63) // 64) * W if lanes else 2 * 2 * H * n
+    return H * W * (1 + 4 + (4 if with_feature else 0)) + inter
 
 
 def algo_bytes(kernel: str, H: int, W: int, n: int, with_dist: bool = True) -> int:
@@ -87,6 +90,8 @@ def algo_bytes(kernel: str, H: int, W: int, n: int, with_dist: bool = True) -> i
         return H * W * 21
     if kernel in ("k_row_segfill", "k_row_segwin"):  # int32 D and F (or D only) out
         return H * W * (8 if with_dist else 4)
+    if kernel == "k_row_lanes":          # bits + carries of listed columns in, D and F out
+        return nb * n * 12 + H * W * (8 if with_dist else 4)
     if kernel.startswith("k_row_"):      # int16 rows in, int32 D and F (or D only) out
         return H * n * 2 + H * W * (8 if with_dist else 4)
     raise KeyError(kernel)
@@ -307,7 +312,8 @@ def path_hbm(nbytes: int, ms: float) -> dict:
     return {"bytes_per_step": int(nbytes), "achieved_GBs": round(gbs, 1),
             "frac": round(gbs / HBM_PEAK_GBS, 4),
             "basis": "mask read once, outputs written once, int16 nearest site row of each "
-                     "column holding a site written and read once"}
+                     "column holding a site written and read once (band bits and carries for "
+                     "batch images of the one-lane-per-row pass)"}
 
 
 def cpu_model() -> str:
@@ -460,7 +466,12 @@ def run_batch(args):
         f"HIP events around every launch (the plan launches its kernels one by one while they "
         f"are on), in a second timed region of {max(3, args.steps // 4)} steps")
     out["roofline"]["scope"] = "the dominant kernel of the step"
-    out["path_hbm"] = path_hbm(sum(path_bytes(m.shape[0], m.shape[1], n)
+    # the images the chosen schedule gives the one-lane-per-row pass
+    knobs = (tune["fixed"] if tune and "fixed" in tune
+             else tune["candidates"][tune["chosen"]] if tune else {"lane_w": 1024})
+    lane_w = knobs["lane_w"]
+    out["path_hbm"] = path_hbm(sum(path_bytes(m.shape[0], m.shape[1], n,
+                                              lanes=m.shape[1] <= lane_w and m.shape[0] <= 4096)
                                    for (m, _), n in zip(imgs, ns)), ms)
     if ms_single is not None:
         out["per_image"] = {"value": round(px / (ms_single * 1e-3) / 1e9, 3),

@@ -37,7 +37,10 @@ int32_t pack_table(const BatchImage* img, int n, int lane_w, uint8_t* dst, int* 
         const int H = img[q].H, W = img[q].W;
         const bool lanes = W <= lane_w && H <= kLanePackMaxH;
         const int tiles = img[q].tr ? items_tiles(W, H) : 0;  // original sides W x H
-        const int64_t items[kPhases] = {items_bits(H, W), items_carry(H, W), 1, items_near(H, W),
+        // images of the lane pass need no site-row lists (the pass works the
+        // rows out from the band bits itself)
+        const int64_t items[kPhases] = {items_bits(H, W), items_carry(H, W), 1,
+                                        lanes ? 0 : items_near(H, W),
                                         lanes ? 0 : H, lanes ? items_lanes(H) : 0, tiles, tiles};
         for (int p = 0; p < kPhases; ++p) {
             int32_t* pre = reinterpret_cast<int32_t*>(dst + img_bytes + p * pre_bytes);

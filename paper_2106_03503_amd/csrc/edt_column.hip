@@ -442,8 +442,9 @@ hipError_t launch_column_pass_batch(const BatchTable& t, const int* totals, hipS
                   dim3(kCarryCols * kCarrySlices), 0, stream, t, totals[kPhCarry]);
     EDT_LAUNCH_AS("k_col_compact", k_compact_batch, grid(totals[kPhCompact]), dim3(1024), 0,
                   stream, t, totals[kPhCompact]);
-    EDT_LAUNCH_AS("k_nearest_row", k_near_batch, wave_grid(totals[kPhNear]),
-                  dim3(64 * kColWaves), 0, stream, t, totals[kPhNear]);
+    if (totals[kPhNear] > 0)  // none when every image takes the lane pass
+        EDT_LAUNCH_AS("k_nearest_row", k_near_batch, wave_grid(totals[kPhNear]),
+                      dim3(64 * kColWaves), 0, stream, t, totals[kPhNear]);
     return launch_status();
 }
 

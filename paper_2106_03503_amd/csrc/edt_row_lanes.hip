@@ -170,6 +170,44 @@ __device__ __forceinline__ void fill_block(int b, const uint32_t* sc, const int1
     }
 }
 
+// Site row of a listed column for the lane's row in the batch kernel, worked
+// out where it is needed instead of read from a list written by a kernel of
+// its own: a work item's 64 rows are one band (kLaneRows == kBand), so the
+// column's band bits and the carries above and below the band (the column
+// pass's own state) give the nearest site at or above the row and the
+// nearest at or below it, and the upper one wins at equal distance, as in the
+// nearest-row pass.  The column is the same in every lane, so the three reads
+// are scalar loads: through the constant address space, which these arrays
+// are while the row pass runs (nothing writes them then).
+struct BandRows {
+    const uint64_t* bits;  // site bits [band][column] (one word each)
+    const int16_t* up;     // [band][column] last site row above the band (-1: none)
+    const int16_t* down;   // [band][column] first site row below it (kNoBelow: none)
+    int64_t b0;            // the band's first element: band * W
+    int row0, r;           // the band's first row and this lane's row in it
+    uint64_t amask;        // bits 0..r
+
+    __device__ __forceinline__ int row_of(int c, int i) const {
+        constexpr int kFar = 1 << 20;  // a missing side: farther than any site
+        typedef const uint64_t __attribute__((address_space(4))) CU64;
+        typedef const uint32_t __attribute__((address_space(4))) CU32;
+        // the int16 carries are read as the aligned 4-byte word holding them
+        // (the arrays start 256-byte aligned; the band's offset may be odd)
+        const int64_t k = b0 + __builtin_amdgcn_readfirstlane(c);
+        const uint64_t m = *reinterpret_cast<CU64*>(reinterpret_cast<uintptr_t>(bits + k));
+        const uint32_t uw = *reinterpret_cast<CU32*>(reinterpret_cast<uintptr_t>(up + (k & ~1ll)));
+        const uint32_t dw =
+            *reinterpret_cast<CU32*>(reinterpret_cast<uintptr_t>(down + (k & ~1ll)));
+        const int u = (int16_t)(uw >> (16 * (k & 1))), dn = (int16_t)(dw >> (16 * (k & 1)));
+        const int ua = u < 0 ? -kFar : u, db = dn == kNoBelow ? kFar : dn;
+        if (m == 0) return 2 * i <= ua + db ? ua : db;  // no site in the band: the same test in every lane
+        const uint64_t above = m & amask, below = m >> r;
+        const int a = above ? row0 + 63 - __clzll(above) : ua;
+        const int d = below ? i + __builtin_ctzll(below) : db;
+        return 2 * i <= a + d ? a : d;
+    }
+};
+
 // Scan of row i (this lane's row): builds the row's envelope as a stack and
 // leaves it in memory, block e / RB at sc + (e / RB) ld (and the unpacked
 // starts at rank e of rr); returns its size.  The
@@ -181,12 +219,14 @@ __device__ __forceinline__ void fill_block(int b, const uint32_t* sc, const int1
 // With kPf the site rows of the next 32 candidates are loaded while the
 // current ones are scanned (16 more registers: the segment scan of single
 // images, whose work items are short, takes it; the batch kernel keeps its
-// registers for occupancy).
-template <bool kPk, bool kPf = false>
+// registers for occupancy).  With kRows the site rows come from br instead of
+// the list rr (the batch kernel).
+template <bool kPk, bool kPf = false, bool kRows = false>
 __device__ __forceinline__ int scan_row(const int i, const int n, const int W,
                                         const int16_t* __restrict__ cols, int16_t* rr,
                                         uint32_t* sc, const int ld, const bool vec,
-                                        LaneRing<kPk>& ring, const int lane, const bool tl) {
+                                        LaneRing<kPk>& ring, const int lane, const bool tl,
+                                        const BandRows br = BandRows{}) {
     int4 pf0, pf1, pf2, pf3;
     if (kPf) {
         pf0 = *reinterpret_cast<const int4*>(rr);
@@ -216,11 +256,13 @@ __device__ __forceinline__ int scan_row(const int i, const int n, const int W,
                 pf2 = *reinterpret_cast<const int4*>(rr + q0 + kBlk + 16);
                 pf3 = *reinterpret_cast<const int4*>(rr + q0 + kBlk + 24);
             }
-        } else {
+        } else if (!kRows) {
             rv0 = *reinterpret_cast<const int4*>(rr + q0);
             rv1 = *reinterpret_cast<const int4*>(rr + q0 + 8);
             rv2 = *reinterpret_cast<const int4*>(rr + q0 + 16);
             rv3 = *reinterpret_cast<const int4*>(rr + q0 + 24);
+        } else {
+            rv0 = rv1 = rv2 = rv3 = make_int4(0, 0, 0, 0);  // not used
         }
         const int4 cv0 = *reinterpret_cast<const int4*>(cols + q0);
         const int4 cv1 = *reinterpret_cast<const int4*>(cols + q0 + 8);
@@ -237,8 +279,9 @@ __device__ __forceinline__ int scan_row(const int i, const int n, const int W,
             for (int u8 = 0; u8 < 8; ++u8) {
                 const int u = 8 * k + u8;
                 if (u >= cnt) break;
-                const int row = (int)((rw[u8 >> 1] >> (16 * (u8 & 1))) & 0xFFFFu);
                 const int col = (int)((cw[u8 >> 1] >> (16 * (u8 & 1))) & 0xFFFFu);
+                const int row = kRows ? br.row_of(col, i)
+                                      : (int)((rw[u8 >> 1] >> (16 * (u8 & 1))) & 0xFFFFu);
                 const int gC = sqr_c(i - row);
                 const int dCe = gC + sqr_c(W - 1 - col);
                 // pop every parabola that the new one beats where it starts
@@ -325,8 +368,8 @@ __global__ __launch_bounds__(kLaneRows) void k_row_lanes_batch(BatchTable tb) {
     const int rows = min(kLaneRows, g.H - i0);
     const Views v = views_of(g);
     const int n = v.meta[0];
-    const int pitch = v.meta[1];
     const int W = g.W;
+    static_assert(kLaneRows == kBand, "a work item's rows are one band");
     // this item's envelopes: block k of row i0 + r at word (k rows + r) RB
     uint32_t* stk = reinterpret_cast<uint32_t*>(g.ws + layout_for(g.H, g.W, false).stk) +
                     (int64_t)i0 * cand_pitch(W);
@@ -335,8 +378,16 @@ __global__ __launch_bounds__(kLaneRows) void k_row_lanes_batch(BatchTable tb) {
                      (g.opitch % 4 == 0);
     if (n > 0 && lane < rows) {
         const int i = i0 + lane;
-        s_m[lane] = scan_row<true>(i, n, W, v.cols, v.rc + (int64_t)i * pitch, stk + lane * RB,
-                                   rows * RB, true, sh.ring, lane, g.tr != 0);
+        BandRows br;
+        br.bits = v.bits;
+        br.up = v.up;
+        br.down = v.down;
+        br.b0 = (int64_t)(i0 / kBand) * W;
+        br.row0 = i0;
+        br.r = lane;
+        br.amask = lane == 63 ? ~0ull : (2ull << lane) - 1ull;
+        s_m[lane] = scan_row<true, false, true>(i, n, W, v.cols, nullptr, stk + lane * RB,
+                                                rows * RB, true, sh.ring, lane, g.tr != 0, br);
     }
     __syncthreads();  // stacks in memory are complete; the ring is free
 
