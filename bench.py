@@ -90,7 +90,7 @@ def algo_bytes(kernel: str, H: int, W: int, n: int, with_dist: bool = True) -> i
         return H * W * 21
     if kernel in ("k_row_segfill", "k_row_segwin"):  # int32 D and F (or D only) out
         return H * W * (8 if with_dist else 4)
-    if kernel == "k_row_lanes":          # bits + carries of listed columns in, D and F out
+    if kernel in ("k_row_lanes", "k_row_sparse"):  # bits + carries of listed columns in, D, F out
         return nb * n * 12 + H * W * (8 if with_dist else 4)
     if kernel.startswith("k_row_"):      # int16 rows in, int32 D and F (or D only) out
         return H * n * 2 + H * W * (8 if with_dist else 4)

@@ -282,12 +282,15 @@ __device__ void compact_item(const Img& g, const Views& v) {
 // above before the band's first site).  Row i takes the upper site a rather
 // than the lower one d when i - a <= d - i -- the upper site wins at equal
 // distance -- i.e. when 2i <= a + d.  A missing side is a site kFar rows away,
-// farther than any real one.  Items past the device-side count n do nothing.
+// farther than any real one.  Items past the device-side count n do nothing,
+// and so does every item of an image with at most kSparseMaxN listed columns:
+// the one-wavefront row form that takes it works its site rows out itself.
 constexpr int kFar = 1 << 20;
 
 __device__ __forceinline__ void near_item(const Img& g, const Views& v, int item, int qblocks,
                                           int lane) {
     const int n = wave_uniform(v.meta[0]);
+    if (n <= kSparseMaxN) return;  // the one-wavefront row form works its rows out itself
     const int pitch = wave_uniform(v.meta[1]);
     const int b = item / qblocks;
     const int q = (item - b * qblocks) * kNearCols + lane;

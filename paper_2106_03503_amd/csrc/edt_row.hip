@@ -387,9 +387,33 @@ __device__ void process_rows(const Img& g, int i0, int i1, int di,
     for (int u = 0; u < S; ++u) colhi[u] = u < cnt ? ((uint32_t)(uint16_t)v.cols[base + u] << 16) : 0u;
 
     for (int i = i0; i < i1; i += di) {
-        // 1. this row's candidates of the chunk: (column, nearest site row)
+        // 1. this row's candidates of the chunk: (column, nearest site row).
+        // The one-wavefront form works the site rows out from the column's
+        // band bits and the carries above and below the band (the nearest
+        // site at or above the row and at or below it, the upper one at equal
+        // distance, as the nearest-row pass does), so that pass has nothing
+        // to do for the images this form takes; the other forms read the
+        // list of site rows it writes.
         const int16_t* rrow = v.rc + (int64_t)i * pitch + base;
-        if (cnt == S) {
+        if (kSparse) {
+            constexpr int kFar = 1 << 20;  // a missing side: farther than any site
+            const int bb = i / kBand, r = i - bb * kBand;
+            const uint64_t amask = r == 63 ? ~0ull : (2ull << r) - 1ull;  // rows 0..r
+            const int64_t b0 = (int64_t)bb * W;
+#pragma unroll 2
+            for (int u = 0; u < S; ++u) {
+                if (u < cnt) {
+                    const int64_t k = b0 + (int)(colhi[u] >> 16);
+                    const uint64_t m = v.bits[k];
+                    const int up = v.up[k], dn = v.down[k];
+                    const uint64_t above = m & amask, below = m >> r;
+                    const int a =
+                        above ? bb * kBand + 63 - __clzll(above) : (up < 0 ? -kFar : up);
+                    const int d = below ? i + __builtin_ctzll(below) : (dn == kNoBelow ? kFar : dn);
+                    sl.c(base + u) = colhi[u] | (uint32_t)(2 * i <= a + d ? a : d);
+                }
+            }
+        } else if (cnt == S) {
             uint32_t w[S / 2];
 #pragma unroll
             for (int q = 0; q < S / 8; ++q) {
