@@ -354,7 +354,9 @@ typedef struct {
     uint64_t launches;           /* groups launched */
     uint64_t pixels_done;        /* sum of H*W over the successful requests */
     double p50_ns, p99_ns, mean_ns, max_ns; /* latency, submission to observed
-                                               completion, over done requests */
+                                               completion: mean and max over
+                                               every done request, p50 and p99
+                                               over the last 65536 of them */
     double gpix_per_s;           /* pixels_done / (last completion - first submission) */
     size_t hbm_in_use;           /* arena bytes held by admitted requests now */
     size_t hbm_high_water;       /* most such bytes ever held at once */
@@ -384,7 +386,9 @@ edt_status edt_serve_submit(edt_server *s, const edt_request *r, uint64_t *ticke
 /* *done (host) = 1 once the ticket has completed, else 0.  Returns the
  * request's own status once done (EDT_OK, or EDT_ERR_DEVICE if its launch
  * failed), EDT_OK while it is pending, EDT_ERR_INVALID_ARG for an unknown
- * ticket. */
+ * ticket.  Every ticket the server issued can be asked about for its whole
+ * life; it keeps an entry per ticket only from the oldest one still in flight
+ * on, plus one per failed ticket. */
 edt_status edt_serve_poll(edt_server *s, uint64_t ticket, int32_t *done);
 
 /* Block until the ticket completes (timeout_ns < 0: no limit) and return its

@@ -33,7 +33,8 @@
 namespace {
 
 using Clock = std::chrono::steady_clock;
-constexpr int32_t kPending = 1;  // request state before completion
+constexpr int32_t kPending = edt::TicketBook::kPending;  // request state before completion
+static_assert(EDT_OK == 0 && kPending != EDT_OK, "the ticket book takes 0 for success");
 
 struct Req {
     uint64_t ticket;
@@ -76,8 +77,7 @@ struct edt_server {
     std::condition_variable done_cv;  // waiters
     std::deque<Req> queue;
     std::vector<hipEvent_t> events;   // idle events
-    std::vector<int32_t> state;       // per ticket - 1: kPending or final status
-    std::vector<double> lat_ns;
+    edt::TicketBook book;             // per-ticket status, latencies
     size_t live = 0;                  // queued or running requests
     bool stop = false;
     bool any = false;
@@ -180,8 +180,8 @@ void finish(edt_server* s, Group& g, int32_t status) {
     {
         std::lock_guard<std::mutex> lk(s->mu);
         for (const Req& q : g.reqs) {
-            s->state[q.ticket - 1] = status;
-            s->lat_ns.push_back(std::chrono::duration<double, std::nano>(now - q.t0).count());
+            s->book.complete(q.ticket, status,
+                             std::chrono::duration<double, std::nano>(now - q.t0).count());
             s->st.done += 1;
             if (status != EDT_OK)
                 s->st.failed += 1;
@@ -372,8 +372,7 @@ edt_status edt_serve_submit(edt_server* s, const edt_request* r, uint64_t* ticke
             s->any = true;
             s->t_first = q.t0;
         }
-        s->state.push_back(kPending);
-        q.ticket = s->state.size();
+        q.ticket = s->book.issue();
         s->queue.push_back(q);
         s->st.submitted += 1;
         *ticket = q.ticket;
@@ -385,8 +384,8 @@ edt_status edt_serve_submit(edt_server* s, const edt_request* r, uint64_t* ticke
 edt_status edt_serve_poll(edt_server* s, uint64_t ticket, int32_t* done) {
     if (!s || !done) return EDT_ERR_INVALID_ARG;
     std::lock_guard<std::mutex> lk(s->mu);
-    if (ticket < 1 || ticket > s->state.size()) return EDT_ERR_INVALID_ARG;
-    const int32_t v = s->state[ticket - 1];
+    if (!s->book.known(ticket)) return EDT_ERR_INVALID_ARG;
+    const int32_t v = s->book.status(ticket);
     *done = v != kPending;
     return v == kPending ? EDT_OK : v;
 }
@@ -394,39 +393,35 @@ edt_status edt_serve_poll(edt_server* s, uint64_t ticket, int32_t* done) {
 edt_status edt_serve_wait(edt_server* s, uint64_t ticket, int64_t timeout_ns) {
     if (!s) return EDT_ERR_INVALID_ARG;
     std::unique_lock<std::mutex> lk(s->mu);
-    if (ticket < 1 || ticket > s->state.size()) return EDT_ERR_INVALID_ARG;
-    auto ready = [&] { return s->state[ticket - 1] != kPending; };
+    if (!s->book.known(ticket)) return EDT_ERR_INVALID_ARG;
+    auto ready = [&] { return s->book.status(ticket) != kPending; };
     if (timeout_ns < 0) {
         s->done_cv.wait(lk, ready);
     } else if (!s->done_cv.wait_for(lk, std::chrono::nanoseconds(timeout_ns), ready)) {
         return EDT_ERR_NOT_READY;
     }
-    return s->state[ticket - 1];
+    return s->book.status(ticket);
 }
 
 edt_status edt_serve_stats(edt_server* s, edt_serve_counters* out) {
     if (!s || !out) return EDT_ERR_INVALID_ARG;
-    // copy under the lock, sort outside it: the scheduler retires requests
-    // and admits new ones under the same lock
+    // copy the (bounded) latency window under the lock, sort outside it: the
+    // scheduler retires requests and admits new ones under the same lock
     std::vector<double> lat;
     edt_serve_counters c;
     double span = 0.0;
     {
         std::lock_guard<std::mutex> lk(s->mu);
         c = s->st;
-        lat = s->lat_ns;
+        lat = s->book.window();
+        const uint64_t n = s->book.completed();
+        c.mean_ns = n ? s->book.latency_sum() / (double)n : 0.0;
+        c.max_ns = s->book.latency_max();
         if (s->any && s->st.done > 0)
             span = std::chrono::duration<double>(s->t_last - s->t_first).count();
     }
     c.p50_ns = edt::percentile(lat, 0.50);
     c.p99_ns = edt::percentile(lat, 0.99);
-    double sum = 0.0, mx = 0.0;
-    for (double v : lat) {
-        sum += v;
-        if (v > mx) mx = v;
-    }
-    c.mean_ns = lat.empty() ? 0.0 : sum / (double)lat.size();
-    c.max_ns = mx;
     c.gpix_per_s = span > 0.0 ? (double)c.pixels_done / span / 1e9 : 0.0;
     *out = c;
     return EDT_OK;

@@ -1,13 +1,17 @@
 // Host-side bookkeeping of the request server that needs no GPU: the arena
-// allocator that carves workspaces out of the caller's device buffer, and the
-// latency percentile.  Plain C++ (no HIP), so that it is also built and tested
-// on its own.
+// allocator that carves workspaces out of the caller's device buffer, the
+// ticket book (request status and latency record) and the latency
+// percentile.  Plain C++ (no HIP), so that it is also built and tested on its
+// own.
 #pragma once
 
 #include <stddef.h>
 
+#include <stdint.h>
+
 #include <algorithm>
 #include <cmath>
+#include <deque>
 #include <map>
 #include <vector>
 
@@ -92,5 +96,60 @@ inline double percentile(std::vector<double> v, double q) {
     if (k > v.size()) k = v.size();
     return v[k - 1];
 }
+
+// Status of every ticket a server has issued (tickets 1, 2, ... in order) and
+// the latencies of the completed requests, in memory bounded by the requests
+// in flight rather than by the server's lifetime: a ticket's entry is dropped
+// once it and every older ticket have completed (a failed one keeps its
+// status in a side map, so any issued ticket can still be asked about), and
+// latencies are kept for the last kWindow completions, with their count, sum
+// and maximum over all completions.  Status codes: kPending while in flight,
+// 0 for success, anything else is a failure.
+class TicketBook {
+public:
+    static constexpr int32_t kPending = 1;
+    static constexpr size_t kWindow = size_t(1) << 16;
+
+    uint64_t issue() {
+        st_.push_back(kPending);
+        return base_ + st_.size() - 1;
+    }
+    bool known(uint64_t t) const { return t >= 1 && t < base_ + st_.size(); }
+    // kPending or the final status of a known ticket.
+    int32_t status(uint64_t t) const {
+        if (t >= base_) return st_[t - base_];
+        const auto it = failed_.find(t);
+        return it == failed_.end() ? 0 : it->second;
+    }
+    // Record the completion of a known, pending ticket.
+    void complete(uint64_t t, int32_t status, double latency) {
+        st_[t - base_] = status;
+        while (!st_.empty() && st_.front() != kPending) {
+            if (st_.front() != 0) failed_[base_] = st_.front();
+            st_.pop_front();
+            ++base_;
+        }
+        if (win_.size() < kWindow)
+            win_.push_back(latency);
+        else
+            win_[n_ % kWindow] = latency;
+        ++n_;
+        sum_ += latency;
+        max_ = std::max(max_, latency);
+    }
+    const std::vector<double>& window() const { return win_; }  // unordered
+    uint64_t completed() const { return n_; }
+    double latency_sum() const { return sum_; }
+    double latency_max() const { return max_; }
+    size_t entries() const { return st_.size() + failed_.size(); }
+
+private:
+    std::deque<int32_t> st_;         // tickets base_, base_ + 1, ...
+    uint64_t base_ = 1;
+    std::map<uint64_t, int32_t> failed_;  // dropped tickets that failed
+    std::vector<double> win_;
+    uint64_t n_ = 0;
+    double sum_ = 0.0, max_ = 0.0;
+};
 
 }  // namespace edt

@@ -159,9 +159,16 @@ def test_serve_too_large_busy_timeout(edt):
         assert torch.equal(D2, Da) and torch.equal(F2, Fa)
         t3 = srv.submit(small)  # room again
         srv.wait(t3, timeout=60)
+        # completed tickets leave the server's book but stay answerable
+        assert srv.poll(t1) and srv.poll(t2) and srv.poll(t3)
+        with pytest.raises(edt.EDTError) as e:
+            srv.poll(t3 + 1)
+        assert e.value.status == -1  # EDT_ERR_INVALID_ARG
         st = srv.stats()
     assert st["rejected_too_large"] == 1 and st["rejected_busy"] == 1
     assert st["done"] == 3 and st["failed"] == 0
+    assert 0 < st["p50_ns"] <= st["p99_ns"] <= st["max_ns"]
+    assert 0 < st["mean_ns"] <= st["max_ns"]
 
 
 def test_serve_wide_rows_run_alone(edt):

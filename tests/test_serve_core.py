@@ -1,6 +1,8 @@
 """Host bookkeeping of the request server, built with g++ and run on the CPU:
 the arena allocator against a byte-map model under random alloc/release
-sequences, and the nearest-rank percentile against its definition."""
+sequences, the ticket book against an unbounded per-ticket model under random
+issue/complete sequences, and the nearest-rank percentile against its
+definition."""
 import os
 import shutil
 import subprocess
@@ -12,6 +14,7 @@ CORE = os.path.join(ROOT, "paper_2106_03503_amd", "csrc")
 
 PROGRAM = r"""
 #include "serve_core.h"
+#include <algorithm>
 #include <cstdio>
 #include <random>
 #include <vector>
@@ -76,6 +79,57 @@ int main() {
             if (a.free_blocks() != runs) return fail("coalesce", a.free_blocks(), runs);
             if (a.largest_free() != largest) return fail("largest", a.largest_free(), largest);
         }
+    }
+    // ticket book: random issues and out-of-order completions (some failing)
+    // against a model that keeps every ticket's status and every latency
+    for (int seed = 0; seed < 8; ++seed) {
+        std::mt19937_64 rng(100 + seed);
+        edt::TicketBook book;
+        std::vector<int> model;      // status of ticket t at t - 1
+        std::vector<uint64_t> open;  // tickets in flight
+        std::vector<double> lats;    // latencies in completion order
+        const int steps = seed < 2 ? 300000 : 20000;  // the first two pass the window
+        for (int step = 0; step < steps; ++step) {
+            if (open.empty() || (open.size() < 64 && rng() % 2)) {
+                const uint64_t t = book.issue();
+                if (t != model.size() + 1) return fail("ticket order", (long)t, (long)model.size());
+                model.push_back(edt::TicketBook::kPending);
+                open.push_back(t);
+            } else {
+                const size_t k = rng() % open.size();
+                const uint64_t t = open[k];
+                open.erase(open.begin() + k);
+                const int st = rng() % 97 == 0 ? -5 : 0;
+                const double lat = (double)(rng() % 1000000);
+                book.complete(t, st, lat);
+                model[t - 1] = st;
+                lats.push_back(lat);
+            }
+            if (step % 997 == 0 || step == steps - 1) {
+                for (uint64_t t = 1; t <= model.size(); ++t)
+                    if (book.status(t) != model[t - 1]) return fail("status", (long)t, model[t - 1]);
+                if (book.known(0) || book.known(model.size() + 1) || !book.known(model.size()))
+                    return fail("known", (long)model.size(), 0);
+                size_t failed = 0;
+                for (int v : model) failed += v != 0 && v != edt::TicketBook::kPending;
+                // entries: from the oldest open ticket on, plus the failures
+                const uint64_t oldest = open.empty() ? model.size() + 1
+                                                     : *std::min_element(open.begin(), open.end());
+                if (book.entries() > model.size() + 1 - oldest + failed)
+                    return fail("bounded", (long)book.entries(), (long)(model.size() + 1 - oldest));
+                if (book.completed() != lats.size()) return fail("count", (long)book.completed(), (long)lats.size());
+                double sum = 0.0, mx = 0.0;
+                for (double v : lats) { sum += v; mx = std::max(mx, v); }
+                if (book.latency_sum() != sum || book.latency_max() != mx) return fail("sum/max", 0, 0);
+                // the window holds exactly the last kWindow latencies
+                const size_t w = std::min(lats.size(), edt::TicketBook::kWindow);
+                std::vector<double> want(lats.end() - (long)w, lats.end()), got = book.window();
+                std::sort(want.begin(), want.end());
+                std::sort(got.begin(), got.end());
+                if (got != want) return fail("window", (long)got.size(), (long)w);
+            }
+        }
+        if (seed < 2 && lats.size() <= edt::TicketBook::kWindow) return fail("window passed", (long)lats.size(), 0);
     }
     // percentile: nearest rank, the smallest value with at least q of the data
     // at or below it
