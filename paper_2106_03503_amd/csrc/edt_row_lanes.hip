@@ -289,61 +289,64 @@ __device__ __forceinline__ int scan_row(const int i, const int n, const int W,
                     const int dC = gC + sqr_c(sA - col);
                     if (!(dC < dAs || (dC == dAs && !tl && row < rowA))) break;
                     --M;
-                    if (M > 0) {
-                        if constexpr (kPk) {
-                            colA = pk_col(cB);
-                            rowA = pk_row(cB);
-                            sA = pk_start(cB);
-                        } else {
-                            colA = (int)(cB >> 16);
-                            rowA = (int)(cB & 0xFFFFu);
-                            sA = sB;
-                        }
-                        gA = sqr_c(i - rowA);
-                        dAs = gA + sqr_c(sA - colA);
-                        dAe = gA + sqr_c(W - 1 - colA);
-                    }
-                    if (M > 1) {
-                        const int e = M - 2;
-                        if (e < base) {  // below the ring: bring its block back
-                            base -= RB;
-                            fill_block<kPk>(base, sc + (base / RB) * ld, rr, vec, ring, lane);
-                        }
-                        cB = ring.c[e & (R - 1)][lane];
-                        if constexpr (!kPk) sB = ring.s[e & (R - 1)][lane];
-                    }
-                }
-                int s = 0;
-                if (M > 0) {
-                    if (!(dCe < dAe || (dCe == dAe && !tl && row < rowA)))
-                        continue;  // never wins in the row
-                    s = first_after(gC - gA + mul_c(col - colA, col + colA) -
-                                        (!tl && row < rowA ? 1 : 0),
-                                    2 * (col - colA), W);
+                    // the entry below becomes the top, and the ring's next
+                    // entry the one below it; both are taken without testing
+                    // M (the ring index stays in range, and what they give is
+                    // read only while M holds them), which spares the
+                    // wavefront two divergent branches per pop
                     if constexpr (kPk) {
-                        cB = pk_entry(colA, sA, rowA);
+                        colA = pk_col(cB);
+                        rowA = pk_row(cB);
+                        sA = pk_start(cB);
                     } else {
-                        cB = ((uint32_t)colA << 16) | (uint32_t)rowA;
-                        sB = sA;
+                        colA = (int)(cB >> 16);
+                        rowA = (int)(cB & 0xFFFFu);
+                        sA = sB;
                     }
+                    gA = sqr_c(i - rowA);
+                    dAs = gA + sqr_c(sA - colA);
+                    dAe = gA + sqr_c(W - 1 - colA);
+                    const int e = M - 2;
+                    if (M > 1 && e < base) {  // below the ring: bring its block back
+                        base -= RB;
+                        fill_block<kPk>(base, sc + (base / RB) * ld, rr, vec, ring, lane);
+                    }
+                    cB = ring.c[e & (R - 1)][lane];
+                    if constexpr (!kPk) sB = ring.s[e & (R - 1)][lane];
                 }
-                if (M - base == R) {  // ring full: its older block goes to memory
-                    spill_block<kPk>(base, sc + (base / RB) * ld, rr, vec, ring, lane);
-                    base += RB;
+                // a parabola that does not beat the top at the row's last
+                // pixel never wins in the row
+                if (M == 0 || dCe < dAe || (dCe == dAe && !tl && row < rowA)) {
+                    int s = 0;
+                    if (M > 0) {
+                        s = first_after(gC - gA + mul_c(col - colA, col + colA) -
+                                            (!tl && row < rowA ? 1 : 0),
+                                        2 * (col - colA), W);
+                        if constexpr (kPk) {
+                            cB = pk_entry(colA, sA, rowA);
+                        } else {
+                            cB = ((uint32_t)colA << 16) | (uint32_t)rowA;
+                            sB = sA;
+                        }
+                    }
+                    if (M - base == R) {  // ring full: its older block goes to memory
+                        spill_block<kPk>(base, sc + (base / RB) * ld, rr, vec, ring, lane);
+                        base += RB;
+                    }
+                    if constexpr (kPk) {
+                        ring.c[M & (R - 1)][lane] = pk_entry(col, s, row);
+                    } else {
+                        ring.c[M & (R - 1)][lane] = ((uint32_t)col << 16) | (uint32_t)row;
+                        ring.s[M & (R - 1)][lane] = (int16_t)s;
+                    }
+                    colA = col;
+                    rowA = row;
+                    gA = gC;
+                    sA = s;
+                    dAs = gC + sqr_c(s - col);
+                    dAe = dCe;
+                    ++M;
                 }
-                if constexpr (kPk) {
-                    ring.c[M & (R - 1)][lane] = pk_entry(col, s, row);
-                } else {
-                    ring.c[M & (R - 1)][lane] = ((uint32_t)col << 16) | (uint32_t)row;
-                    ring.s[M & (R - 1)][lane] = (int16_t)s;
-                }
-                colA = col;
-                rowA = row;
-                gA = gC;
-                sA = s;
-                dAs = gC + sqr_c(s - col);
-                dAe = dCe;
-                ++M;
             }
         }
     }
