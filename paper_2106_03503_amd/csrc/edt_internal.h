@@ -244,23 +244,21 @@ __device__ __forceinline__ int sqr_c(int x) { return __mul24(x, x); }
 
 // floor(num / den) + 1, clamped to [0, W], for 2 <= den < 2^16, num < 2^31
 // and W < 2^15: a float estimate of the quotient (relative error below 2^-21,
-// so within one of the floor wherever the result is below W), corrected with
-// the integer remainder.  It is the first pixel from which a parabola beats
-// its left neighbour when num/den is their intersection (Eq. eq_intersection,
-// with den = 2 (l - k)).  A host model of these steps, with the hardware
+// so within one of the floor wherever the result is below W), clamped to W
+// (an estimate past W means a floor of at least W, which the correction then
+// keeps), corrected by one from the integer remainder, and 0 for a negative
+// num; written without branches, so that the lanes of a wavefront taking it
+// with different operands do not diverge.  It is the first pixel from which
+// a parabola beats its left neighbour when num/den is their intersection
+// (Eq. eq_intersection, with den = 2 (l - k)).  A host model of these steps, with the hardware
 // reciprocal off by up to two ulp, gives the exact floor for every den in
 // [2, 2^16) and W below 2^15 at each multiple of den and its neighbours.
 __device__ __forceinline__ int first_after(int num, int den, int W) {
-    if (num < 0) return 0;
     const float qf = (float)num * __builtin_amdgcn_rcpf((float)den);
-    int q = (int)qf;
-    if (q > W) return W;
+    const int q = min((int)qf, W);  // an estimate past W has a floor of at least W
     const int r = num - mul_c(q, den);
-    if (r < 0)
-        --q;
-    else if (r >= den)
-        ++q;
-    return min(q + 1, W);
+    const int qc = q + (r >= den ? 1 : 0) - (r < 0 ? 1 : 0);
+    return min(qc + 1, W) & ~(num >> 31);  // 0 for a negative num
 }
 
 // A device address as a pointer into global memory.  Going through the

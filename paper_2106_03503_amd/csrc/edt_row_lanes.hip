@@ -285,9 +285,12 @@ __device__ __forceinline__ int scan_row(const int i, const int n, const int W,
                 const int gC = sqr_c(i - row);
                 const int dCe = gC + sqr_c(W - 1 - col);
                 // pop every parabola that the new one beats where it starts
+                // (the tests over lane values are bitwise, not && and ||:
+                // short-circuit evaluation would cost the wavefront a
+                // divergent branch per test)
                 while (M > 0) {
                     const int dC = gC + sqr_c(sA - col);
-                    if (!(dC < dAs || (dC == dAs && !tl && row < rowA))) break;
+                    if (!((dC < dAs) | ((dC == dAs) & !tl & (row < rowA)))) break;
                     --M;
                     // the entry below becomes the top, and the ring's next
                     // entry the one below it; both are taken without testing
@@ -307,7 +310,7 @@ __device__ __forceinline__ int scan_row(const int i, const int n, const int W,
                     dAs = gA + sqr_c(sA - colA);
                     dAe = gA + sqr_c(W - 1 - colA);
                     const int e = M - 2;
-                    if (M > 1 && e < base) {  // below the ring: bring its block back
+                    if ((M > 1) & (e < base)) {  // below the ring: bring its block back
                         base -= RB;
                         fill_block<kPk>(base, sc + (base / RB) * ld, rr, vec, ring, lane);
                     }
@@ -316,18 +319,19 @@ __device__ __forceinline__ int scan_row(const int i, const int n, const int W,
                 }
                 // a parabola that does not beat the top at the row's last
                 // pixel never wins in the row
-                if (M == 0 || dCe < dAe || (dCe == dAe && !tl && row < rowA)) {
-                    int s = 0;
-                    if (M > 0) {
-                        s = first_after(gC - gA + mul_c(col - colA, col + colA) -
-                                            (!tl && row < rowA ? 1 : 0),
-                                        2 * (col - colA), W);
-                        if constexpr (kPk) {
-                            cB = pk_entry(colA, sA, rowA);
-                        } else {
-                            cB = ((uint32_t)colA << 16) | (uint32_t)rowA;
-                            sB = sA;
-                        }
+                if ((M == 0) | (dCe < dAe) | ((dCe == dAe) & !tl & (row < rowA))) {
+                    // the start is worked out by every lane that pushes and
+                    // zeroed where the stack was empty (its operands are then
+                    // stale, and nothing in it can fault)
+                    const bool below = M > 0;
+                    const int s = first_after(gC - gA + mul_c(col - colA, col + colA) -
+                                                  ((!tl & (row < rowA)) ? 1 : 0),
+                                              2 * (col - colA), W) & -(int)below;
+                    if constexpr (kPk) {
+                        cB = below ? pk_entry(colA, sA, rowA) : cB;
+                    } else {
+                        cB = below ? ((uint32_t)colA << 16) | (uint32_t)rowA : cB;
+                        sB = below ? sA : sB;
                     }
                     if (M - base == R) {  // ring full: its older block goes to memory
                         spill_block<kPk>(base, sc + (base / RB) * ld, rr, vec, ring, lane);

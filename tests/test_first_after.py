@@ -1,10 +1,10 @@
 """Host model of the row passes' division (first_after in edt_internal.h): the
 first pixel past an intersection of Eq. eq_intersection, floor(num / den) + 1
 clamped to [0, W], computed from a float estimate of the quotient (num and
-the reciprocal of den rounded to fp32, their product rounded to fp32 and
-truncated) and one integer correction step.  The hardware reciprocal is
-accurate to about one ulp; here it is modelled as the correctly rounded
-reciprocal moved by -2 .. +2 ulp, and the result must equal the exact floor
+the reciprocal of den rounded to fp32, their product rounded to fp32,
+truncated, then clamped to W) and one integer correction step.  The hardware
+reciprocal is accurate to about one ulp; here it is modelled as the correctly
+rounded reciprocal moved by -2 .. +2 ulp, and the result must equal the exact floor
 for every denominator 2 <= den < 2^16, for W up to 2^15 - 1, at the numerators
 where an error would show: each multiple of den and its neighbours, for
 quotients across the whole clamped range, and the largest numerators below
@@ -23,13 +23,10 @@ def model(num, den, W, ulps):
         for _ in range(abs(ulps)):
             rcp = np.nextafter(rcp, toward).astype(np.float32)
     qf = (num.astype(np.float32) * rcp).astype(np.float32)
-    q = np.trunc(qf).astype(np.int64)
-    over = q > W
+    q = np.minimum(np.trunc(qf).astype(np.int64), W)
     r = num - q * den
-    q = np.where(r < 0, q - 1, np.where(r >= den, q + 1, q))
-    out = np.minimum(q + 1, W)
-    out = np.where(over, W, out)
-    return np.where(num < 0, 0, out)
+    q = q + (r >= den) - (r < 0)
+    return np.where(num < 0, 0, np.minimum(q + 1, W))
 
 
 def exact(num, den, W):
