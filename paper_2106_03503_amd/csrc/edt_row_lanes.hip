@@ -436,15 +436,19 @@ __global__ __launch_bounds__(kLaneRows) void k_row_lanes_batch(BatchTable tb) {
                 }
             } else {
                 // owner of pixel j: the last entry starting at or before it,
-                // searched from this lane's previous owner
+                // searched from this lane's previous owner (reads past the
+                // envelope are clamped to its last entry and their result
+                // discarded, so that no read needs a branch of its own)
                 int step = 1;
-                while (e + step < M && pk_start(sh.row.c[e + step]) <= j) {
-                    e += step;
+                for (;;) {
+                    const int x = e + step;
+                    if (!((x < M) & (pk_start(sh.row.c[min(x, M - 1)]) <= j))) break;
+                    e = x;
                     step <<= 1;
                 }
                 e = last_at_or_before(sh.row.c, e, min(M, e + step), j);
                 uint32_t c = sh.row.c[e];
-                int nst = e + 1 < M ? pk_start(sh.row.c[e + 1]) : INT32_MAX;
+                int nst = e + 1 < M ? pk_start(sh.row.c[min(e + 1, M - 1)]) : INT32_MAX;
 #pragma unroll
                 for (int q = 0; q < 4; ++q) {
                     const int jj = j + q;
@@ -454,7 +458,7 @@ __global__ __launch_bounds__(kLaneRows) void k_row_lanes_batch(BatchTable tb) {
                         while (jj >= nst) {
                             ++e;
                             c = sh.row.c[e];
-                            nst = e + 1 < M ? pk_start(sh.row.c[e + 1]) : INT32_MAX;
+                            nst = e + 1 < M ? pk_start(sh.row.c[min(e + 1, M - 1)]) : INT32_MAX;
                         }
                         const int col = pk_col(c), row = pk_row(c);
                         d[q] = sqr_c(i - row) + sqr_c(jj - col);
