@@ -246,16 +246,19 @@ __device__ __forceinline__ int sqr_c(int x) { return __mul24(x, x); }
 // and W < 2^15: a float estimate of the quotient (relative error below 2^-21,
 // so within one of the floor wherever the result is below W), clamped to W
 // (an estimate past W means a floor of at least W, which the correction then
-// keeps), corrected by one from the integer remainder, and 0 for a negative
-// num; written without branches, so that the lanes of a wavefront taking it
-// with different operands do not diverge.  It is the first pixel from which
+// keeps; below by -1), corrected by one from the integer remainder, and 0 for
+// a negative num; written without branches, so that the lanes of a wavefront
+// taking it with different operands do not diverge, and defined for any
+// operands.  It is the first pixel from which
 // a parabola beats its left neighbour when num/den is their intersection
 // (Eq. eq_intersection, with den = 2 (l - k)).  A host model of these steps, with the hardware
 // reciprocal off by up to two ulp, gives the exact floor for every den in
 // [2, 2^16) and W below 2^15 at each multiple of den and its neighbours.
 __device__ __forceinline__ int first_after(int num, int den, int W) {
     const float qf = (float)num * __builtin_amdgcn_rcpf((float)den);
-    const int q = min((int)qf, W);  // an estimate past W has a floor of at least W
+    // an estimate past W has a floor of at least W; clamping before the
+    // conversion also keeps it defined for any operands
+    const int q = (int)__builtin_amdgcn_fmed3f(qf, -1.0f, (float)W);
     const int r = num - mul_c(q, den);
     const int qc = q + (r >= den ? 1 : 0) - (r < 0 ? 1 : 0);
     return min(qc + 1, W) & ~(num >> 31);  // 0 for a negative num

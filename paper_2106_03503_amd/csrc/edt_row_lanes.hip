@@ -208,6 +208,10 @@ struct BandRows {
     }
 };
 
+// a + b, wrapping: the pop loop also unpacks stale ring slots, whose sums are
+// never used but must not overflow
+__device__ __forceinline__ int wrap_add(int a, int b) { return (int)((uint32_t)a + (uint32_t)b); }
+
 // Scan of row i (this lane's row): builds the row's envelope as a stack and
 // leaves it in memory, block e / RB at sc + (e / RB) ld (and the unpacked
 // starts at rank e of rr); returns its size.  The
@@ -307,8 +311,8 @@ __device__ __forceinline__ int scan_row(const int i, const int n, const int W,
                         sA = sB;
                     }
                     gA = sqr_c(i - rowA);
-                    dAs = gA + sqr_c(sA - colA);
-                    dAe = gA + sqr_c(W - 1 - colA);
+                    dAs = wrap_add(gA, sqr_c(sA - colA));
+                    dAe = wrap_add(gA, sqr_c(W - 1 - colA));
                     const int e = M - 2;
                     if ((M > 1) & (e < base)) {  // below the ring: bring its block back
                         base -= RB;
@@ -322,11 +326,13 @@ __device__ __forceinline__ int scan_row(const int i, const int n, const int W,
                 if ((M == 0) | (dCe < dAe) | ((dCe == dAe) & !tl & (row < rowA))) {
                     // the start is worked out by every lane that pushes and
                     // zeroed where the stack was empty (its operands are then
-                    // stale, and nothing in it can fault)
+                    // stale: nothing in it can fault, and the numerator wraps
+                    // rather than overflows)
                     const bool below = M > 0;
-                    const int s = first_after(gC - gA + mul_c(col - colA, col + colA) -
-                                                  ((!tl & (row < rowA)) ? 1 : 0),
-                                              2 * (col - colA), W) & -(int)below;
+                    const uint32_t num = (uint32_t)gC - (uint32_t)gA +
+                                         (uint32_t)mul_c(col - colA, col + colA) -
+                                         ((!tl & (row < rowA)) ? 1u : 0u);
+                    const int s = first_after((int)num, 2 * (col - colA), W) & -(int)below;
                     if constexpr (kPk) {
                         cB = below ? pk_entry(colA, sA, rowA) : cB;
                     } else {

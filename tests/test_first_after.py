@@ -2,7 +2,7 @@
 first pixel past an intersection of Eq. eq_intersection, floor(num / den) + 1
 clamped to [0, W], computed from a float estimate of the quotient (num and
 the reciprocal of den rounded to fp32, their product rounded to fp32,
-truncated, then clamped to W) and one integer correction step.  The hardware
+clamped to [-1, W], then truncated) and one integer correction step.  The hardware
 reciprocal is accurate to about one ulp; here it is modelled as the correctly
 rounded reciprocal moved by -2 .. +2 ulp, and the result must equal the exact floor
 for every denominator 2 <= den < 2^16, for W up to 2^15 - 1, at the numerators
@@ -23,7 +23,7 @@ def model(num, den, W, ulps):
         for _ in range(abs(ulps)):
             rcp = np.nextafter(rcp, toward).astype(np.float32)
     qf = (num.astype(np.float32) * rcp).astype(np.float32)
-    q = np.minimum(np.trunc(qf).astype(np.int64), W)
+    q = np.trunc(np.clip(qf, np.float32(-1.0), np.float32(W))).astype(np.int64)
     r = num - q * den
     q = q + (r >= den) - (r < 0)
     return np.where(num < 0, 0, np.minimum(q + 1, W))
