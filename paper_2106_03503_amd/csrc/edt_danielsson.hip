@@ -11,9 +11,14 @@
 //
 // The result depends on the order of the offers pixel by pixel, so a row's
 // sweeps are one sequential chain: one workgroup of one wavefront takes the
-// whole image, the vertical offers and the row transfers on all 64 lanes, the
-// sweeps on lane 0 in LDS.  This is the approximate comparison, not a hot
-// path.  Relative positions travel packed as (dy << 16) | dx, -1 = unreached.
+// whole image, the vertical offers and the row transfers on all 64 lanes.  A
+// sweep takes the row 64 pixels at a time into the lanes' registers and walks
+// them in order, reading each pixel and its diagonal neighbour out of their
+// lanes, taking the offers in scalar registers (a dependent step there costs
+// a cycle or two, where the vector unit of a lone wavefront takes several)
+// and writing the result back into the pixel's lane.  This is the approximate
+// comparison, not a hot path.  Relative positions travel packed as
+// (dy << 16) | dx, -1 = unreached.
 #include "../../include/edt.h"
 #include "edt_internal.h"
 
@@ -21,8 +26,8 @@ namespace edt {
 namespace {
 
 constexpr int kDanMaxW = 8192;  // two rows of packed positions in LDS
-// The offers are one chain of about 4 H W steps on one lane (about 0.8 us per
-// thousand pixels): images are capped so that a call stays within seconds.
+// The offers are one chain of about 4 H W steps: images are capped so that a
+// call stays within seconds.
 constexpr int64_t kDanMaxPixels = (int64_t)1 << 22;
 
 __device__ __forceinline__ int d2_of(int32_t p) {
@@ -31,21 +36,71 @@ __device__ __forceinline__ int d2_of(int32_t p) {
 }
 
 // The pixel holding `cur` takes `from` plus (ay, ax) when strictly nearer.
+// Stored offsets stay within the image, so an offer is at most one past it;
+// the field test only keeps a 16-bit field from overflowing.  One select and
+// no branch:
+// the sweeps run this as a chain of scalar instructions, where every branch
+// would stall the lone wavefront.
 __device__ __forceinline__ int32_t offer(int32_t cur, int32_t from, int ay, int ax) {
-    if (from < 0) return cur;
-    const int ny = (from >> 16) + ay, nx = (from & 0xFFFF) + ax;
-    // stored offsets stay within the image, so an offer is at most one past
-    // it; the guard only keeps a 16-bit field from overflowing
-    if (ny > 0x7FFF || nx > 0x7FFF) return cur;
+    const int32_t f = from < 0 ? 0 : from, c = cur < 0 ? 0 : cur;  // squares stay in range
+    const int ny = (f >> 16) + ay, nx = (f & 0xFFFF) + ax;
     const int nd = sqr_c(ny) + sqr_c(nx);
-    if (cur >= 0 && d2_of(cur) <= nd) return cur;
-    return (ny << 16) | nx;
+    const bool take = (from >= 0) & (ny <= 0x7FFF) & (nx <= 0x7FFF) &
+                      ((cur < 0) | (d2_of(c) > nd));
+    return take ? (ny << 16) | nx : cur;
 }
 
 __device__ __forceinline__ int32_t initial(const uint8_t* mask, int64_t mpitch, int pol, int i,
                                            int j) {
     const bool obj = mask[(int64_t)i * mpitch + j] != 0;
     return (pol ? !obj : obj) ? 0 : -1;
+}
+
+// Left-to-right sweep of row `cur` (both scans): pixel j takes its left
+// neighbour's position plus (0, 1), then the upper (first scan) or lower
+// (second scan) left neighbour's plus (1, 1), from `prev`.
+__device__ void sweep_right(int32_t* cur, const int32_t* prev, int W, int lane) {
+    int32_t v = -1;
+    for (int base = 0; base < W; base += 64) {
+        const int j = base + lane;
+        const int32_t x = j < W ? cur[j] : -1;
+        const int32_t pd = j < W && j > 0 ? prev[j - 1] : -1;
+        int32_t out = x;
+        const int cnt = min(64, W - base);
+        for (int k = base == 0 ? 1 : 0; k < cnt; ++k) {
+            if (base == 0 && k == 1) v = __builtin_amdgcn_readlane(x, 0);
+            v = offer(offer(__builtin_amdgcn_readlane(x, k), v, 0, 1),
+                      __builtin_amdgcn_readlane(pd, k), 1, 1);
+            out = lane == k ? v : out;
+        }
+        if (j < W) cur[j] = out;
+    }
+}
+
+// Right-to-left sweep: pixel j takes the right neighbour's position plus
+// (0, 1) and the upper or lower right neighbour's plus (1, 1), the diagonal
+// first in the first scan (kDiagFirst) and second in the second.
+template <bool kDiagFirst>
+__device__ void sweep_left(int32_t* cur, const int32_t* prev, int W, int lane) {
+    int32_t v = -1;
+    for (int base = (W - 1) & ~63; base >= 0; base -= 64) {
+        const int j = base + lane;
+        const int32_t x = j < W ? cur[j] : -1;
+        const int32_t pd = j + 1 < W ? prev[j + 1] : -1;
+        int32_t out = x;
+        const int top = min(64, W - base) - 1;  // the chunk's last pixel
+        for (int k = top; k >= 0; --k) {
+            if (base + k == W - 1) {
+                v = __builtin_amdgcn_readlane(x, k);
+                continue;
+            }
+            const int32_t c = __builtin_amdgcn_readlane(x, k);
+            const int32_t d = __builtin_amdgcn_readlane(pd, k);
+            v = kDiagFirst ? offer(offer(c, d, 1, 1), v, 0, 1) : offer(offer(c, v, 0, 1), d, 1, 1);
+            out = lane == k ? v : out;
+        }
+        if (j < W) cur[j] = out;
+    }
 }
 
 __global__ __launch_bounds__(64) void k_danielsson(const uint8_t* mask, int64_t mpitch, int H,
@@ -70,18 +125,8 @@ __global__ __launch_bounds__(64) void k_danielsson(const uint8_t* mask, int64_t 
         for (int j = lane; j < W; j += 64)
             cur[j] = offer(initial(mask, mpitch, pol, i, j), prev[j], 1, 0);
         __syncthreads();
-        if (lane == 0) {
-            int32_t v = cur[0];
-            for (int j = 1; j < W; ++j) {
-                v = offer(offer(cur[j], v, 0, 1), prev[j - 1], 1, 1);
-                cur[j] = v;
-            }
-            v = cur[W - 1];
-            for (int j = W - 2; j >= 0; --j) {
-                v = offer(offer(cur[j], prev[j + 1], 1, 1), v, 0, 1);
-                cur[j] = v;
-            }
-        }
+        sweep_right(cur, prev, W, lane);
+        sweep_left<true>(cur, prev, W, lane);
         __syncthreads();
         for (int j = lane; j < W; j += 64) rel[(int64_t)i * opitch + j] = cur[j];
         swap_rows();
@@ -93,18 +138,8 @@ __global__ __launch_bounds__(64) void k_danielsson(const uint8_t* mask, int64_t 
         for (int j = lane; j < W; j += 64)
             cur[j] = offer(rel[(int64_t)i * opitch + j], prev[j], 1, 0);
         __syncthreads();
-        if (lane == 0) {
-            int32_t v = cur[0];
-            for (int j = 1; j < W; ++j) {
-                v = offer(offer(cur[j], v, 0, 1), prev[j - 1], 1, 1);
-                cur[j] = v;
-            }
-            v = cur[W - 1];
-            for (int j = W - 2; j >= 0; --j) {
-                v = offer(offer(cur[j], v, 0, 1), prev[j + 1], 1, 1);
-                cur[j] = v;
-            }
-        }
+        sweep_right(cur, prev, W, lane);
+        sweep_left<false>(cur, prev, W, lane);
         __syncthreads();
         for (int j = lane; j < W; j += 64) rel[(int64_t)i * opitch + j] = cur[j];
         swap_rows();

@@ -53,6 +53,19 @@ def test_random_masks(edt, seed):
         assert np.array_equal(R, Ro), (H, W, pol)
 
 
+@pytest.mark.parametrize("shape", [(3, 8192), (5, 4160), (4, 127)])
+def test_widest_rows(edt, shape):
+    # rows of the largest width the call takes, and widths just past and
+    # short of a multiple of 64: the sweeps walk a row 64 pixels at a time
+    H, W = shape
+    m = (np.random.default_rng(W).random((H, W)) < 0.001).astype(np.uint8)
+    m[0, W // 3] = 1
+    for pol in (0, 1):
+        D, R = _run(edt, m, pol)
+        Do, Ro = oracle.danielsson(m, pol)
+        assert np.array_equal(D, Do) and np.array_equal(R, Ro), (H, W, pol)
+
+
 def test_disks_512(edt):
     m = workloads.disks(512, 512, n_disks=30, rmin=3, rmax=40)
     for pol in (0, 1):
