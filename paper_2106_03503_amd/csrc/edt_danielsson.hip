@@ -56,21 +56,70 @@ __device__ __forceinline__ int32_t initial(const uint8_t* mask, int64_t mpitch, 
     return (pol ? !obj : obj) ? 0 : -1;
 }
 
+// A sweep's chain carries the running position v packed, with its squared
+// length vd.  Per chunk of 64 pixels the lanes first work out, for their own
+// pixel, the squared length of its position (INT32_MAX when unreached) and the
+// diagonal neighbour's offer: its position plus (1, 1) packed (-1 when the
+// neighbour is unreached or a field would pass 0x7FFF) and its squared length.
+// An offer of v plus (0, 1) is then v + 1 with length vd + 2 x + 1, so a step
+// is a few scalar instructions.  Each offer is taken when strictly nearer,
+// exactly as offer() decides.
+struct Chunk {
+    int32_t c, cd, dp, dd;  // this lane's pixel and its length; diagonal offer and its length
+};
+
+__device__ __forceinline__ Chunk chunk_of(int32_t c, int32_t diag) {
+    Chunk k;
+    k.c = c;
+    k.cd = c < 0 ? INT32_MAX : d2_of(c);
+    const int32_t f = diag < 0 ? 0 : diag;
+    const int ny = (f >> 16) + 1, nx = (f & 0xFFFF) + 1;
+    const bool ok = (diag >= 0) & (ny <= 0x7FFF) & (nx <= 0x7FFF);
+    k.dp = ok ? (ny << 16) | nx : -1;
+    k.dd = sqr_c(ny) + sqr_c(nx);
+    return k;
+}
+
+// The pixel (p, pd) takes v plus (0, 1) when strictly nearer.
+__device__ __forceinline__ void take_side(int32_t& p, int32_t& pd, int32_t v, int32_t vd) {
+    const int vx = v & 0xFFFF;
+    const int nd = vd + 2 * vx + 1;
+    const bool t = (v >= 0) & (vx < 0x7FFF) & (pd > nd);
+    p = t ? v + 1 : p;
+    pd = t ? nd : pd;
+}
+
+// The pixel (p, pd) takes the diagonal offer (dp, dd) when strictly nearer.
+__device__ __forceinline__ void take_diag(int32_t& p, int32_t& pd, int32_t dp, int32_t dd) {
+    const bool t = (dp >= 0) & (pd > dd);
+    p = t ? dp : p;
+    pd = t ? dd : pd;
+}
+
 // Left-to-right sweep of row `cur` (both scans): pixel j takes its left
 // neighbour's position plus (0, 1), then the upper (first scan) or lower
 // (second scan) left neighbour's plus (1, 1), from `prev`.
 __device__ void sweep_right(int32_t* cur, const int32_t* prev, int W, int lane) {
-    int32_t v = -1;
+    int32_t v = -1, vd = INT32_MAX;
     for (int base = 0; base < W; base += 64) {
         const int j = base + lane;
-        const int32_t x = j < W ? cur[j] : -1;
-        const int32_t pd = j < W && j > 0 ? prev[j - 1] : -1;
-        int32_t out = x;
+        const Chunk ch = chunk_of(j < W ? cur[j] : -1, j < W && j > 0 ? prev[j - 1] : -1);
+        int32_t out = ch.c;
         const int cnt = min(64, W - base);
-        for (int k = base == 0 ? 1 : 0; k < cnt; ++k) {
-            if (base == 0 && k == 1) v = __builtin_amdgcn_readlane(x, 0);
-            v = offer(offer(__builtin_amdgcn_readlane(x, k), v, 0, 1),
-                      __builtin_amdgcn_readlane(pd, k), 1, 1);
+        int k = 0;
+        if (base == 0) {  // pixel 0 starts the chain as it is
+            v = __builtin_amdgcn_readlane(ch.c, 0);
+            vd = __builtin_amdgcn_readlane(ch.cd, 0);
+            k = 1;
+        }
+        for (; k < cnt; ++k) {
+            int32_t p = __builtin_amdgcn_readlane(ch.c, k);
+            int32_t pd = __builtin_amdgcn_readlane(ch.cd, k);
+            take_side(p, pd, v, vd);
+            take_diag(p, pd, __builtin_amdgcn_readlane(ch.dp, k),
+                      __builtin_amdgcn_readlane(ch.dd, k));
+            v = p;
+            vd = pd;
             out = lane == k ? v : out;
         }
         if (j < W) cur[j] = out;
@@ -82,21 +131,31 @@ __device__ void sweep_right(int32_t* cur, const int32_t* prev, int W, int lane) 
 // first in the first scan (kDiagFirst) and second in the second.
 template <bool kDiagFirst>
 __device__ void sweep_left(int32_t* cur, const int32_t* prev, int W, int lane) {
-    int32_t v = -1;
+    int32_t v = -1, vd = INT32_MAX;
     for (int base = (W - 1) & ~63; base >= 0; base -= 64) {
         const int j = base + lane;
-        const int32_t x = j < W ? cur[j] : -1;
-        const int32_t pd = j + 1 < W ? prev[j + 1] : -1;
-        int32_t out = x;
-        const int top = min(64, W - base) - 1;  // the chunk's last pixel
-        for (int k = top; k >= 0; --k) {
-            if (base + k == W - 1) {
-                v = __builtin_amdgcn_readlane(x, k);
-                continue;
+        const Chunk ch = chunk_of(j < W ? cur[j] : -1, j + 1 < W ? prev[j + 1] : -1);
+        int32_t out = ch.c;
+        int k = min(64, W - base) - 1;
+        if (base + k == W - 1) {  // pixel W - 1 starts the chain as it is
+            v = __builtin_amdgcn_readlane(ch.c, k);
+            vd = __builtin_amdgcn_readlane(ch.cd, k);
+            --k;
+        }
+        for (; k >= 0; --k) {
+            int32_t p = __builtin_amdgcn_readlane(ch.c, k);
+            int32_t pd = __builtin_amdgcn_readlane(ch.cd, k);
+            const int32_t dp = __builtin_amdgcn_readlane(ch.dp, k);
+            const int32_t dd = __builtin_amdgcn_readlane(ch.dd, k);
+            if (kDiagFirst) {
+                take_diag(p, pd, dp, dd);
+                take_side(p, pd, v, vd);
+            } else {
+                take_side(p, pd, v, vd);
+                take_diag(p, pd, dp, dd);
             }
-            const int32_t c = __builtin_amdgcn_readlane(x, k);
-            const int32_t d = __builtin_amdgcn_readlane(pd, k);
-            v = kDiagFirst ? offer(offer(c, d, 1, 1), v, 0, 1) : offer(offer(c, v, 0, 1), d, 1, 1);
+            v = p;
+            vd = pd;
             out = lane == k ? v : out;
         }
         if (j < W) cur[j] = out;
