@@ -191,6 +191,19 @@ edt_status edt_danielsson(const uint8_t *mask, int32_t H, int32_t W, int64_t mas
                           int32_t polarity, int32_t *dist_sq, int32_t *rel,
                           int64_t out_pitch, void *stream);
 
+/* Euclidean distances in fp32 written by the row pass itself, with no second
+ * pass over the output (Section 3.1 takes the square root once the squared
+ * distances are known): dist holds the square root of the squared Euclidean
+ * distance edt_sq computes, rounded exactly as edt_sqrt_f32 rounds it, and
+ * +infinity where the image has no site.  Same arguments as edt_feature
+ * without metric, with
+ *   dist        device, fp32, H x W with row pitch out_pitch elements; written
+ *   feature     device or NULL: int32 nearest-site indices, as edt_feature
+ * Errors as edt_feature; EDT_ERR_INVALID_ARG when dist is NULL. */
+edt_status edt_dist_f32(const uint8_t *mask, int32_t H, int32_t W, int64_t mask_pitch,
+                        int32_t polarity, float *dist, int32_t *feature, int64_t out_pitch,
+                        void *workspace, size_t workspace_bytes, void *stream);
+
 /* d = sqrt(D) drawn after all squared distances are known (Section 3.1):
  * computed in fp64 and rounded to fp32 (the nearest fp32 to the true root for
  * every D < 2^31); EDT_INF_SQ maps to +infinity.  dist_sq and dist are device

@@ -34,5 +34,6 @@ from ._lib import (  # noqa: F401
     regions,
     sq,
     sqrt_f32,
+    dist_f32,
     workspace_bytes,
 )

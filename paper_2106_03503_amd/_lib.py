@@ -53,6 +53,8 @@ def _load():
     lib.edt_feature_noalloc.restype = i32
     lib.edt_sqrt_f32.argtypes = [P, P, i64, P]
     lib.edt_sqrt_f32.restype = i32
+    lib.edt_dist_f32.argtypes = [P, i32, i32, i64, i32, P, P, i64, P, sz, P]
+    lib.edt_dist_f32.restype = i32
     lib.edt_regions.argtypes = [P, i32, i32, i64, i32, i32, P, P, i64, P]
     lib.edt_regions.restype = i32
     lib.edt_danielsson.argtypes = [P, i32, i32, i64, i32, P, P, i64, P]
@@ -198,6 +200,32 @@ def sqrt_f32(dist_sq: torch.Tensor, out: torch.Tensor | None = None, stream=None
     _check(_lib.edt_sqrt_f32(dist_sq.data_ptr(), out.data_ptr(), dist_sq.numel(),
                              _stream_ptr(stream)), "edt_sqrt_f32")
     return out
+
+
+def dist_f32(mask: torch.Tensor, polarity: int = EDT_TO_OBJECT, want_feature: bool = False,
+             out_dist: torch.Tensor | None = None, out_feat: torch.Tensor | None = None,
+             workspace: torch.Tensor | None = None, stream=None):
+    """(float32 Euclidean distance, nearest-site index or None), the distance
+    written by the row pass itself: equal to sqrt_f32 of edt.sq's result."""
+    mask = _check_mask(mask)
+    H, W = mask.shape
+    if out_dist is None:
+        D = torch.empty((H, W), dtype=torch.float32, device=mask.device)
+    elif (out_dist.dtype != torch.float32 or out_dist.shape != (H, W)
+          or out_dist.device != mask.device or out_dist.stride(1) != 1):
+        raise ValueError(f"out_dist must be a float32 {H}x{W} tensor on {mask.device} "
+                         "with unit column stride")
+    else:
+        D = out_dist
+    F = _check_out(out_feat, H, W, mask.device, "out_feat") if want_feature else None
+    if F is not None and D.stride(0) != F.stride(0):
+        raise ValueError("out_dist and out_feat must share one row pitch")
+    ws = _workspace(H, W, want_feature, mask.device, workspace)
+    _check(_lib.edt_dist_f32(mask.data_ptr(), H, W, mask.stride(0), polarity, D.data_ptr(),
+                             F.data_ptr() if F is not None else None, D.stride(0),
+                             ws.data_ptr(), ws.numel() * ws.element_size(),
+                             _stream_ptr(stream)), "edt_dist_f32")
+    return D, F
 
 
 def regions(mask: torch.Tensor, feature: torch.Tensor, polarity: int = EDT_TO_OBJECT,

@@ -44,8 +44,7 @@ __global__ __launch_bounds__(256) void k_sqrt(const int32_t* __restrict__ D,
                                               float* __restrict__ out, int64_t n) {
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < n; q += stride) {
-        const int32_t d = D[q];
-        out[q] = d == INT32_MAX ? INFINITY : (float)sqrt((double)d);
+        out[q] = __int_as_float(sqrt_bits(D[q]));
     }
 }
 
@@ -71,7 +70,7 @@ edt_status check_image(const uint8_t* mask, int32_t H, int32_t W, int64_t mask_p
 static edt_status run(const uint8_t* mask, int32_t H, int32_t W, int64_t mask_pitch,
                       int32_t polarity, int32_t metric, int32_t* dist, int32_t* feat,
                       int64_t out_pitch, void* workspace, size_t workspace_bytes,
-                      void* stream) {
+                      void* stream, bool fsq = false) {
     edt_status st = check_image(mask, H, W, mask_pitch, polarity, metric, out_pitch);
     if (st != EDT_OK) return st;
     if (!dist && !feat) return EDT_ERR_INVALID_ARG;
@@ -90,6 +89,7 @@ static edt_status run(const uint8_t* mask, int32_t H, int32_t W, int64_t mask_pi
     g.W = W;
     g.pol = polarity;
     g.metric = metric;
+    g.fsq = fsq ? 1 : 0;
     return enqueue_single(g, s) == hipSuccess ? EDT_OK : EDT_ERR_DEVICE;
 }
 
@@ -156,6 +156,15 @@ edt_status edt_feature_noalloc(const uint8_t* mask, int32_t H, int32_t W, int64_
     if (edt::scratch_address(&ws) != hipSuccess) return EDT_ERR_DEVICE;
     return edt::run(mask, H, W, mask_pitch, polarity, metric, dist_sq, feature, out_pitch, ws,
                     (size_t)EDT_NOALLOC_SCRATCH_BYTES, stream);
+}
+
+edt_status edt_dist_f32(const uint8_t* mask, int32_t H, int32_t W, int64_t mask_pitch,
+                        int32_t polarity, float* dist, int32_t* feature, int64_t out_pitch,
+                        void* workspace, size_t workspace_bytes, void* stream) {
+    if (!dist) return EDT_ERR_INVALID_ARG;
+    return edt::run(mask, H, W, mask_pitch, polarity, EDT_METRIC_EUCLIDEAN_SQ,
+                    reinterpret_cast<int32_t*>(dist), feature, out_pitch, workspace,
+                    workspace_bytes, stream, true);
 }
 
 edt_status edt_sqrt_f32(const int32_t* dist_sq, float* dist, int64_t n, void* stream) {

@@ -118,6 +118,9 @@ struct Img {
     int H, W, pol;
     int metric;        // EDT_METRIC_*: 0 squared Euclidean, 1 city-block, 2 chessboard,
                        // 3 chamfer 4-3
+    int fsq = 0;       // dist receives fp32 Euclidean distances (sqrt_bits of the squared
+                       // ones) instead of int32 squared distances: single images,
+                       // squared Euclidean metric, through kernels compiled for it
     int tr = 0;        // a batch image processed as its transpose: H, W, mask and
                        // outputs are the transposed ones (in its workspace), ties in
                        // the row pass go to the left column (the smaller original
@@ -262,6 +265,14 @@ __device__ __forceinline__ int first_after(int num, int den, int W) {
     const int r = num - mul_c(q, den);
     const int qc = q + (r >= den ? 1 : 0) - (r < 0 ? 1 : 0);
     return min(qc + 1, W) & ~(num >> 31);  // 0 for a negative num
+}
+
+// The fp32 Euclidean distance of a squared distance, as int32 bits for the
+// output stores: the fp64 square root rounded to fp32 (the nearest fp32 to the
+// true root for every d < 2^31), and +infinity for INT32_MAX (no site).
+__device__ __forceinline__ int32_t sqrt_bits(int32_t d) {
+    const float f = d == INT32_MAX ? __builtin_inff() : (float)sqrt((double)d);
+    return __float_as_int(f);
 }
 
 // A device address as a pointer into global memory.  Going through the

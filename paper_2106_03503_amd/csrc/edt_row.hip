@@ -285,7 +285,7 @@ __device__ __forceinline__ void store4(int32_t* __restrict__ p, int j, int W, bo
 // Fill row i from its envelope (M survivors in column order: candidates in
 // cand, first owned pixels in st), four adjacent pixels per lane and store, so
 // that a wavefront writes 1 KiB of contiguous output per instruction.
-template <int kM, int T>
+template <int kM, int T, bool kF = false>
 __device__ __forceinline__ void fill_row(const Img& g, int i, const uint32_t* cand,
                                          const int16_t* st, int M, bool vec, const TieCtx& tc) {
     const int W = g.W;
@@ -324,7 +324,13 @@ __device__ __forceinline__ void fill_row(const Img& g, int i, const uint32_t* ca
                 }
             }
         }
-        if (drow) store4(drow, j, W, vec, d[0], d[1], d[2], d[3]);
+        if (drow) {
+            if constexpr (kF) {
+#pragma unroll
+                for (int q = 0; q < 4; ++q) d[q] = sqrt_bits(d[q]);
+            }
+            store4(drow, j, W, vec, d[0], d[1], d[2], d[3]);
+        }
         if (frow) store4(frow, j, W, vec, f[0], f[1], f[2], f[3]);
     }
 }
@@ -350,7 +356,7 @@ __device__ __forceinline__ bool form_takes(int n, int W) {
     return n > kSparseMaxN && W > T * S / 2 && W <= T * S;
 }
 
-template <int kM, int T, int S, bool kSparse, bool kGlobal>
+template <int kM, int T, int S, bool kSparse, bool kGlobal, bool kF>
 __device__ void process_rows(const Img& g, int i0, int i1, int di,
                              RowLds<T, S, kSparse, kGlobal>& sh, uint8_t* gslot) {
     constexpr int NW = T / 64;
@@ -504,17 +510,18 @@ __device__ void process_rows(const Img& g, int i0, int i1, int di,
         }
         __syncthreads();
         // 5. fill, four adjacent pixels per lane and step
-        fill_row<kM, T>(g, i, cand, st, M, vec, tc);
+        fill_row<kM, T, kF>(g, i, cand, st, M, vec, tc);
         __syncthreads();  // the next row reuses the list and the chunk tables
     }
 }
 
-// One image: rows blockIdx.x, blockIdx.x + gridDim.x, ...
-template <int kM, int T, int S, bool kSparse, bool kGlobal>
+// One image: rows blockIdx.x, blockIdx.x + gridDim.x, ...  With kF the
+// distances are written as fp32 Euclidean distances (sqrt_bits).
+template <int kM, int T, int S, bool kSparse, bool kGlobal, bool kF = false>
 __global__ __launch_bounds__(T) void k_row_single(Img g, uint8_t* __restrict__ slots) {
     __shared__ RowLds<T, S, kSparse, kGlobal> sh;
     uint8_t* gslot = kGlobal ? slots + (size_t)blockIdx.x * wide_slot_bytes() : nullptr;
-    process_rows<kM, T, S, kSparse, kGlobal>(g, blockIdx.x, g.H, gridDim.x, sh, gslot);
+    process_rows<kM, T, S, kSparse, kGlobal, kF>(g, blockIdx.x, g.H, gridDim.x, sh, gslot);
 }
 
 // Dense rows of one image after the segment scan: the envelope of segment c
@@ -614,7 +621,7 @@ __device__ __forceinline__ int seg_at(const int16_t* first, int nseg, int x) {
     return a;
 }
 
-template <int L>
+template <int L, bool kF = false>
 __global__ __launch_bounds__(kWinLanes) void k_row_segwin(Img g, SegBufs sb) {
     __shared__ WinLds<L> sh;
     constexpr int kPer = WinShape<L>::kPer;
@@ -760,7 +767,13 @@ __global__ __launch_bounds__(kWinLanes) void k_row_segwin(Img g, SegBufs sb) {
                 far = farthest();
             }
             if (!ok) break;
-            if (drow) store4(drow, j, W, vec, bd[0], bd[1], bd[2], bd[3]);
+            if (drow) {
+                if constexpr (kF) {
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) bd[q] = sqrt_bits(bd[q]);
+                }
+                store4(drow, j, W, vec, bd[0], bd[1], bd[2], bd[3]);
+            }
             if (frow) store4(frow, j, W, vec, bf[0], bf[1], bf[2], bf[3]);
         }
         if (!ok) sb.rowfail[i] = 1;
@@ -781,7 +794,7 @@ struct SegLds {
     int wsum[T / 64];
 };
 
-template <int T, int L>
+template <int T, int L, bool kF = false>
 __global__ __launch_bounds__(T, T <= 512 ? 6 : 1) void k_row_segfill(Img g, SegBufs sb) {
     __shared__ SegLds<T, L> sh;
     constexpr int CAP = SegLds<T, L>::CAP, NW = T / 64, PER = CAP / T;
@@ -892,7 +905,7 @@ __global__ __launch_bounds__(T, T <= 512 ? 6 : 1) void k_row_segfill(Img g, SegB
             }
         }
         __syncthreads();
-        fill_row<0, T>(g, i, sh.cand, sh.st, M, vec, tc);
+        fill_row<0, T, kF>(g, i, sh.cand, sh.st, M, vec, tc);
         __syncthreads();  // the next row reuses the tables
     }
 }
@@ -915,7 +928,7 @@ __global__ __launch_bounds__(T) void k_row_batch(BatchTable tb, int total) {
         const Img g = batch_img(tb, im);
         const int r0 = item - tb.prefix[kPhRows][im];
         const int r1 = min(g.H, end - tb.prefix[kPhRows][im]);
-        process_rows<0, T, S, kSparse, false>(g, r0, r1, 1, sh, nullptr);
+        process_rows<0, T, S, kSparse, false, false>(g, r0, r1, 1, sh, nullptr);
         item += r1 - r0;
     }
 }
@@ -929,16 +942,16 @@ int blocks_per_cu(K kernel, int threads) {
     return nb;
 }
 
-template <int kM, int T, int S, bool kSparse, bool kGlobal>
+template <int kM, int T, int S, bool kSparse, bool kGlobal, bool kF = false>
 hipError_t launch_single(const Img& g, uint8_t* slots, hipStream_t stream) {
     static int per_cu = 0;
-    if (per_cu == 0) per_cu = blocks_per_cu(k_row_single<kM, T, S, kSparse, kGlobal>, T);
+    if (per_cu == 0) per_cu = blocks_per_cu(k_row_single<kM, T, S, kSparse, kGlobal, kF>, T);
     int grid = per_cu * device_cus();
     if (kGlobal && grid > kWideSlots) grid = kWideSlots;
     if (grid > g.H) grid = g.H;
     const char* name = kSparse ? "k_row_sparse" : (kGlobal ? "k_row_dense_global" : "k_row_dense");
-    EDT_LAUNCH_AS(name, (k_row_single<kM, T, S, kSparse, kGlobal>), dim3(grid), dim3(T), 0, stream,
-                  g, slots);
+    EDT_LAUNCH_AS(name, (k_row_single<kM, T, S, kSparse, kGlobal, kF>), dim3(grid), dim3(T), 0,
+                  stream, g, slots);
     return launch_status();
 }
 
@@ -954,36 +967,38 @@ hipError_t launch_batch(const BatchTable& tb, int total, hipStream_t stream) {
     return launch_status();
 }
 
-template <int T, int L>
+template <int T, int L, bool kF>
 hipError_t launch_segfill(const Img& g, const SegBufs& sb, hipStream_t stream) {
     static int per_cu = 0;
-    if (per_cu == 0) per_cu = blocks_per_cu(k_row_segfill<T, L>, T);
+    if (per_cu == 0) per_cu = blocks_per_cu(k_row_segfill<T, L, kF>, T);
     int grid = per_cu * device_cus();
     if (grid > g.H) grid = g.H;
-    EDT_LAUNCH_AS("k_row_segfill", (k_row_segfill<T, L>), dim3(grid), dim3(T), 0, stream, g, sb);
+    EDT_LAUNCH_AS("k_row_segfill", (k_row_segfill<T, L, kF>), dim3(grid), dim3(T), 0, stream, g,
+                  sb);
     return launch_status();
 }
 
-template <int L>
+template <int L, bool kF>
 hipError_t launch_segwin(const Img& g, const SegBufs& sb, hipStream_t stream) {
     static int per_cu = 0;
-    if (per_cu == 0) per_cu = blocks_per_cu(k_row_segwin<L>, kWinLanes);
+    if (per_cu == 0) per_cu = blocks_per_cu(k_row_segwin<L, kF>, kWinLanes);
     const int total = g.H * ((g.W + kWinTile - 1) / kWinTile);
     const int grid = min(total, per_cu * device_cus());
-    EDT_LAUNCH_AS("k_row_segwin", k_row_segwin<L>, dim3(grid), dim3(kWinLanes), 0, stream, g, sb);
+    EDT_LAUNCH_AS("k_row_segwin", (k_row_segwin<L, kF>), dim3(grid), dim3(kWinLanes), 0, stream,
+                  g, sb);
     return launch_status();
 }
 
-template <int L>
+template <int L, bool kF>
 hipError_t launch_segments_l(const Img& g, const SegBufs& sb, hipStream_t stream) {
     hipError_t e = launch_row_segscan(g, L, sb, stream);
-    if (e == hipSuccess) e = launch_segwin<L>(g, sb, stream);
+    if (e == hipSuccess) e = launch_segwin<L, kF>(g, sb, stream);
     if (e != hipSuccess) return e;
     const int W = g.W;
-    if (W <= 2048) return launch_segfill<128, L>(g, sb, stream);
-    if (W <= 4096) return launch_segfill<256, L>(g, sb, stream);
-    if (W <= 8192) return launch_segfill<512, L>(g, sb, stream);
-    return launch_segfill<1024, L>(g, sb, stream);
+    if (W <= 2048) return launch_segfill<128, L, kF>(g, sb, stream);
+    if (W <= 4096) return launch_segfill<256, L, kF>(g, sb, stream);
+    if (W <= 8192) return launch_segfill<512, L, kF>(g, sb, stream);
+    return launch_segfill<1024, L, kF>(g, sb, stream);
 }
 
 // Dense rows of one image, squared Euclidean: segment scan, the bounded
@@ -994,33 +1009,39 @@ hipError_t launch_segments_l(const Img& g, const SegBufs& sb, hipStream_t stream
 // search: 2.47 ms with 128, 2.33 with 256, 2.19 with 512 and 2.71 with 1024,
 // 128 having beaten 64 there by 0.3 ms; on 4096^2 disks the longer ones are
 // slower: too few scan items).
+template <bool kF>
 hipError_t launch_rows_segments(const Img& g, hipStream_t stream) {
     const SegBufs sb = seg_bufs(g);
     auto items = [&](int L) { return (int64_t)items_lanes(g.H) * ((g.W + L - 1) / L); };
-    if (items(8 * kSegL) >= 4096) return launch_segments_l<8 * kSegL>(g, sb, stream);
-    if (items(4 * kSegL) >= 4096) return launch_segments_l<4 * kSegL>(g, sb, stream);
-    if (items(2 * kSegL) >= 4096) return launch_segments_l<2 * kSegL>(g, sb, stream);
-    return launch_segments_l<kSegL>(g, sb, stream);
+    if (items(8 * kSegL) >= 4096) return launch_segments_l<8 * kSegL, kF>(g, sb, stream);
+    if (items(4 * kSegL) >= 4096) return launch_segments_l<4 * kSegL, kF>(g, sb, stream);
+    if (items(2 * kSegL) >= 4096) return launch_segments_l<2 * kSegL, kF>(g, sb, stream);
+    return launch_segments_l<kSegL, kF>(g, sb, stream);
 }
 
-template <int kM>
+// kF (squared Euclidean only): distances written as fp32 Euclidean ones; the
+// kernels without it compile exactly as if the option did not exist.
+template <int kM, bool kF = false>
 hipError_t launch_rows_metric(const Img& g, uint8_t* slots, hipStream_t stream) {
+    static_assert(!kF || kM == 0, "fp32 distances are Euclidean only");
     // Both forms are enqueued; each returns at once unless the image's number
     // of candidate columns (known only on the device) is in its range.
-    hipError_t e = launch_single<kM, kSparseLanes, kRowS, true, false>(g, slots, stream);
+    hipError_t e = launch_single<kM, kSparseLanes, kRowS, true, false, kF>(g, slots, stream);
     const int W = g.W;
     if (e != hipSuccess || W <= kSparseMaxN) return e;
-    if (kM == 0 && has_segments(W)) return launch_rows_segments(g, stream);
-    if (W <= 2048) return launch_single<kM, 128, kRowS, false, false>(g, slots, stream);
-    if (W <= 4096) return launch_single<kM, 256, kRowS, false, false>(g, slots, stream);
-    if (W <= 8192) return launch_single<kM, 512, kRowS, false, false>(g, slots, stream);
-    if (W <= kLdsMaxW) return launch_single<kM, 1024, kRowS, false, false>(g, slots, stream);
-    return launch_single<kM, 1024, 2 * kRowS, false, true>(g, slots, stream);
+    if (kM == 0 && has_segments(W)) return launch_rows_segments<kF>(g, stream);
+    if (W <= 2048) return launch_single<kM, 128, kRowS, false, false, kF>(g, slots, stream);
+    if (W <= 4096) return launch_single<kM, 256, kRowS, false, false, kF>(g, slots, stream);
+    if (W <= 8192) return launch_single<kM, 512, kRowS, false, false, kF>(g, slots, stream);
+    if (W <= kLdsMaxW) return launch_single<kM, 1024, kRowS, false, false, kF>(g, slots, stream);
+    return launch_single<kM, 1024, 2 * kRowS, false, true, kF>(g, slots, stream);
 }
 
 }  // namespace
 
 hipError_t launch_row_pass(const Img& g, uint8_t* slots, hipStream_t stream) {
+    if (g.fsq) return g.metric == 0 ? launch_rows_metric<0, true>(g, slots, stream)
+                                    : hipErrorInvalidValue;
     if (g.metric == 1) return launch_rows_metric<1>(g, slots, stream);
     if (g.metric == 2) return launch_rows_metric<2>(g, slots, stream);
     if (g.metric == 3) return launch_rows_metric<3>(g, slots, stream);

@@ -79,6 +79,13 @@ def test_argument_validation_returns_before_any_launch(edt):
     assert lib.edt_sq(fake, 10, 10, 10, 0, 0, fake, 10, fake, ws - 1, None) == -1
     assert lib.edt_sq(fake, 10, 10, 10, 0, 0, fake, 10, None, ws, None) == -1
     assert lib.edt_sq(fake, 10, 10, 10, 0, 0, fake, 10, fake + 8, ws, None) == -1
+    # fp32 distances: a distance output is required; sizes, pitches and the
+    # workspace as for edt_sq
+    assert lib.edt_dist_f32(fake, 10, 10, 10, 0, None, fake, 10, fake, ws, None) == -1
+    assert lib.edt_dist_f32(fake, 0, 10, 10, 0, fake, None, 10, fake, ws, None) == -3
+    assert lib.edt_dist_f32(fake, 10, 10, 10, 0, fake, None, 9, fake, ws, None) == -1
+    assert lib.edt_dist_f32(fake, 10, 10, 10, 2, fake, None, 10, fake, ws, None) == -1
+    assert lib.edt_dist_f32(fake, 10, 10, 10, 0, fake, None, 10, fake, ws - 1, None) == -1
     # region labels: sizes, pointers, pitches, enums, overlap of labels with the inputs
     big = 0x10000000
     assert lib.edt_regions(fake, 0, 10, 10, 0, 8, fake, big, 10, None) == -3
