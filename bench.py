@@ -13,6 +13,9 @@ Workloads (--workload):
   dense16k             a 16384 x 16384 image of 3200 random disks (the 4096^2
                        disk image's density over 16 times the area);
   points16k_sq         the same image through edt_sq (distances only);
+  points16k_f32, dense16k_f32
+                       the points and dense images through edt_dist_f32 (fp32
+                       Euclidean distances written by the row pass, and features);
   disks4k, disks4k_inside, bernoulli256
   disks4k_regions      the disks image through edt_feature and then edt_regions
   disks1k_danielsson   a 1024^2 disks image through Danielsson's approximate transform,
@@ -113,6 +116,15 @@ SINGLE = {
         H=16384, W=16384, polarity=0, call="edt_sq",
         desc="16384x16384 uint8 mask, 30 uniform random object points; int32 squared "
              "distance only (edt_sq)"),
+    "points16k_f32": dict(
+        H=16384, W=16384, polarity=0, call="edt_dist_f32",
+        desc="16384x16384 uint8 mask, 30 uniform random object points; fp32 Euclidean "
+             "distance written by the row pass + int32 nearest-object index (edt_dist_f32)"),
+    "dense16k_f32": dict(
+        H=16384, W=16384, polarity=0, call="edt_dist_f32",
+        desc="16384x16384 uint8 mask, 3200 random filled disks (r 5-200) + Bernoulli(1e-4) "
+             "points; fp32 Euclidean distance written by the row pass + int32 nearest-object "
+             "index (edt_dist_f32)"),
     "disks4k": dict(
         H=4096, W=4096, polarity=0,
         desc="4096x4096 uint8 mask, 200 random filled disks (r 5-200) + Bernoulli(1e-4) "
@@ -155,9 +167,9 @@ SERVE_DESC = ("{n} requests arriving as a Poisson stream at {rate:g}/s: square u
 
 def make_mask(name):
     import workloads
-    if name in ("points16k", "points16k_sq"):
+    if name in ("points16k", "points16k_sq", "points16k_f32"):
         return workloads.points(16384, 16384, 30)
-    if name == "dense16k":
+    if name in ("dense16k", "dense16k_f32"):
         return workloads.disks(16384, 16384, n_disks=3200)
     if name.startswith("disks4k"):
         return workloads.disks(4096, 4096)
@@ -357,8 +369,14 @@ def run_single(args):
     L = torch.empty((H, W), dtype=torch.int32, device=dev) if conn else None
 
     dan = wl.get("call") == "edt_danielsson"
+    f32 = wl.get("call") == "edt_dist_f32"
+    Df = torch.empty((H, W), dtype=torch.float32, device=dev) if f32 else None
 
     def step():
+        if f32:
+            edt.dist_f32(mask, polarity=pol, want_feature=True, out_dist=Df, out_feat=F,
+                         workspace=ws, stream=stream)
+            return
         if dan:
             edt.danielsson(mask, polarity=pol, out_dist=D, out_rel=F, stream=stream)
             return
@@ -378,7 +396,7 @@ def run_single(args):
     px = H * W
     out = base_line(args, px / (ms * 1e-3) / 1e9, ms,
                     {"workload": wl["desc"], "H": H, "W": W, "polarity": pol,
-                     "call": "edt_danielsson" if dan else (
+                     "call": "edt_danielsson" if dan else "edt_dist_f32" if f32 else (
                          ("edt_sq" if sq_only else "edt_feature")
                          + (f" + edt_regions ({conn}-neighbourhood)" if conn else "")),
                      "metric": "Danielsson's approximate squared distance" if dan else
