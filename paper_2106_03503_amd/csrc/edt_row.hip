@@ -516,9 +516,11 @@ __device__ void process_rows(const Img& g, int i0, int i1, int di,
 }
 
 // One image: rows blockIdx.x, blockIdx.x + gridDim.x, ...  With kF the
-// distances are written as fp32 Euclidean distances (sqrt_bits).
+// distances are written as fp32 Euclidean distances (sqrt_bits); the sparse
+// form then asks for 5 waves per SIMD, as it reaches without the conversion
+// (its fp64 square root would otherwise take it to 102 VGPRs and 4 waves).
 template <int kM, int T, int S, bool kSparse, bool kGlobal, bool kF = false>
-__global__ __launch_bounds__(T) void k_row_single(Img g, uint8_t* __restrict__ slots) {
+__global__ __launch_bounds__(T, (kF && kSparse) ? 5 : 1) void k_row_single(Img g, uint8_t* __restrict__ slots) {
     __shared__ RowLds<T, S, kSparse, kGlobal> sh;
     uint8_t* gslot = kGlobal ? slots + (size_t)blockIdx.x * wide_slot_bytes() : nullptr;
     process_rows<kM, T, S, kSparse, kGlobal, kF>(g, blockIdx.x, g.H, gridDim.x, sh, gslot);
