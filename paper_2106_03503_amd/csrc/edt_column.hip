@@ -270,6 +270,7 @@ __device__ void compact_item(const Img& g, const Views& v) {
     if (t == 0) {
         v.meta[0] = total;
         v.meta[1] = cand_pitch(total > 0 ? total : 1);
+        v.meta[2] = 0;  // the segment search's count of claimed work items
     }
 }
 

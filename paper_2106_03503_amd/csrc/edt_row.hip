@@ -623,12 +623,15 @@ __device__ __forceinline__ int seg_at(const int16_t* first, int nseg, int x) {
     return a;
 }
 
+// Up to 128-candidate segments the LDS copy leaves room for 5 workgroups per
+// CU, and the kernel is held to the registers of 5 waves per SIMD (96, with no
+// spills); the longer segments' copy allows 4.
 template <int L, bool kF = false>
-__global__ __launch_bounds__(kWinLanes) void k_row_segwin(Img g, SegBufs sb) {
+__global__ __launch_bounds__(kWinLanes, L <= 128 ? 5 : 1) void k_row_segwin(Img g, SegBufs sb) {
     __shared__ WinLds<L> sh;
     constexpr int kPer = WinShape<L>::kPer;
     static_assert(L >= 16, "a 16-pixel step crosses at most one segment start");
-    __shared__ int s_lo, s_hi;
+    __shared__ int s_lo, s_hi, s_next;
     const Views v = views_of(g);
     const int n = v.meta[0];
     if (n <= kSparseMaxN) return;  // the one-wavefront row pass took the image
@@ -646,11 +649,21 @@ __global__ __launch_bounds__(kWinLanes) void k_row_segwin(Img g, SegBufs sb) {
         sh.first[c] = v.cols[c * L];
         sh.last[c] = v.cols[min((c + 1) * L, n) - 1];
     }
-    for (int item = blockIdx.x; item < total; item += gridDim.x) {
+    // With many items per workgroup they are taken in the order workgroups
+    // claim them: each workgroup's first is its own index, and while working
+    // on one it claims the next from a counter (zeroed by the column-list
+    // pass), so that rows of uneven cost spread over the workgroups as they
+    // free up.  With few, the claim's latency (its first load waits for it:
+    // loads and atomics share one counter) costs more than the balance gains,
+    // and a workgroup takes every gridDim.x-th item.
+    const bool claimed = total >= 16 * (int)gridDim.x;
+    for (int item = blockIdx.x; item < total;) {
         const int i = item / ntiles;
         const int x0 = (item - i * ntiles) * kWinTile, x1 = min(W, x0 + kWinTile);
         __syncthreads();  // the previous item is done with the LDS copy
+        int claim = 0;
         if (t == 0) {
+            if (claimed) claim = atomicAdd(&v.meta[2], 1);
             s_lo = max(0, seg_at(sh.first, nseg, x0) - win_halo<L>());
             s_hi = min(nseg - 1, seg_at(sh.first, nseg, x1 - 1) + win_halo<L>());
         }
@@ -779,6 +792,9 @@ __global__ __launch_bounds__(kWinLanes) void k_row_segwin(Img g, SegBufs sb) {
             if (frow) store4(frow, j, W, vec, bf[0], bf[1], bf[2], bf[3]);
         }
         if (!ok) sb.rowfail[i] = 1;
+        if (t == 0) s_next = claimed ? (int)gridDim.x + claim : item + (int)gridDim.x;
+        __syncthreads();
+        item = s_next;
     }
 }
 
