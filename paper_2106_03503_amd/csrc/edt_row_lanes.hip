@@ -291,10 +291,12 @@ __device__ __forceinline__ int scan_row(const int i, const int n, const int W,
                 // pop every parabola that the new one beats where it starts
                 // (the tests over lane values are bitwise, not && and ||:
                 // short-circuit evaluation would cost the wavefront a
-                // divergent branch per test)
-                while (M > 0) {
-                    const int dC = gC + sqr_c(sA - col);
-                    if (!((dC < dAs) | ((dC == dAs) & !tl & (row < rowA)))) break;
+                // divergent branch per test; and the loop has one exit, the
+                // stack size tested with the rest, so that a lane leaving it
+                // costs one level of exec-mask bookkeeping, not two)
+                for (;;) {
+                    const int dC = wrap_add(gC, sqr_c(sA - col));
+                    if (!((M > 0) & ((dC < dAs) | ((dC == dAs) & !tl & (row < rowA))))) break;
                     --M;
                     // the entry below becomes the top, and the ring's next
                     // entry the one below it; both are taken without testing
